@@ -1,0 +1,214 @@
+/*
+ * C interface of the MI355X (gfx950) renderer for grid-based NeRF with
+ * sparse radiance warping (SpaRW), after arXiv 2404.11852.
+ *
+ * General conventions (every entry point):
+ *  - All array pointers are DEVICE pointers owned by the caller; the library
+ *    never allocates or frees device memory.  Scratch memory is passed in as
+ *    a workspace (ws, ws_bytes); its required size comes from
+ *    cic_workspace_bytes().  Contents of the workspace are undefined after a
+ *    call; it may be reused by the next call on the same stream.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  No call synchronises the host; counts the GPU produces stay
+ *    in device memory.
+ *  - Arguments are validated on the host before anything is launched.
+ *    Return value: CIC_OK (0), or a negative code: CIC_ERR_INVALID (-1) bad
+ *    argument, CIC_ERR_WORKSPACE (-2) workspace too small, CIC_ERR_HIP (-3)
+ *    HIP runtime error (launch failure), CIC_ERR_DEVICE (-4) the current
+ *    device is not gfx950.  cic_last_error_message() describes the last
+ *    failure of the calling thread.
+ *  - Gradient outputs of render_backward are ACCUMULATED (+=); the caller
+ *    zeroes them.
+ *  - Calls that share a workspace must not overlap (same stream, or
+ *    ordered by the caller).
+ *
+ * Data layout:
+ *  - Grid: vertices on the corners of the box [box_lo, box_hi] ("align
+ *    corners"), res[a] vertices per axis.  density is the raw (pre-
+ *    activation) value, [res0][res1][res2] with the last index fastest;
+ *    features are [res0][res1][res2][n_feat], channel fastest.  Storage is
+ *    float32 or float16 (IEEE binary16) for both.
+ *  - Occupancy: one byte per voxel, [(res0-1)][(res1-1)][(res2-1)],
+ *    nonzero = occupied (see build_occupancy).
+ *  - MLP weights: float32 row-major [out][in]; inputs are the interpolated
+ *    features, the view direction and its sinusoidal encoding.
+ *  - Rays: rays_o, rays_d float32 [n][3]; directions are expected to be unit
+ *    length (distances are measured in units of |d|).
+ *  - Frames: pixel p = j*width + i (row j, column i); rgb float32 [H*W][3].
+ *  - Cameras: OpenCV axes (x right, y down, z forward); c2w is row-major
+ *    3x4 [R | eye]; pixel centres at (i + 1/2, j + 1/2).
+ */
+#ifndef CICERO_H
+#define CICERO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *cic_stream_t; /* hipStream_t */
+
+enum {
+    CIC_OK = 0,
+    CIC_ERR_INVALID = -1,
+    CIC_ERR_WORKSPACE = -2,
+    CIC_ERR_HIP = -3,
+    CIC_ERR_DEVICE = -4
+};
+
+/* storage / compute types */
+enum { CIC_F32 = 0, CIC_F16 = 1, CIC_BF16 = 2 };
+
+/* sample processing order for the feature gather + MLP stage */
+enum { CIC_ORDER_RAY = 0, CIC_ORDER_VOXEL = 1 };
+
+/* operations, for cic_workspace_bytes */
+enum {
+    CIC_OP_RENDER_RAYS = 0,
+    CIC_OP_RENDER_FRAME = 1,
+    CIC_OP_WARP_FRAME = 2,
+    CIC_OP_RENDER_FRAME_SPARW = 3,
+    CIC_OP_RENDER_BACKWARD = 4
+};
+
+typedef struct {
+    int32_t res[3];            /* vertices per axis, each in [2, 2048] */
+    int32_t n_feat;            /* feature channels; must be 12 */
+    int32_t storage;           /* CIC_F32 or CIC_F16 (density and features) */
+    float box_lo[3];
+    float box_hi[3];
+    float density_shift;       /* added to the interpolated raw density before softplus */
+    const void *density;       /* device, [res0][res1][res2] */
+    const void *features;      /* device, [res0][res1][res2][n_feat] */
+    const uint8_t *occupancy;  /* device, [(res0-1)(res1-1)(res2-1)], or NULL */
+} cic_grid;
+
+typedef struct {
+    int32_t compute;           /* CIC_F32 (FP32 MFMA) or CIC_BF16 (BF16 MFMA, FP32 accumulate) */
+    int32_t in_dim;            /* n_feat + 3 + 6*pe_freqs; must be 39 */
+    int32_t hidden;            /* must be 128 */
+    int32_t pe_freqs;          /* must be 4 */
+    const float *w0, *b0;      /* device, [hidden][in_dim], [hidden] */
+    const float *w1, *b1;      /* device, [hidden][hidden], [hidden] */
+    const float *w2, *b2;      /* device, [3][hidden], [3] */
+} cic_mlp;
+
+typedef struct {
+    int32_t n_samples;         /* samples per ray, 1..1024 */
+    float et_threshold;        /* early termination: stop once transmittance < this; 0 = off */
+    int32_t use_occupancy;     /* skip voxels whose occupancy byte is 0 (needs grid.occupancy) */
+    float bg[3];               /* background colour added with weight T_stop */
+    float void_acc;            /* frames: z-depth is +inf where opacity < void_acc */
+    int32_t order;             /* CIC_ORDER_RAY or CIC_ORDER_VOXEL */
+} cic_opts;
+
+typedef struct {
+    int32_t width, height;     /* pixels, each in [1, 16384] */
+    float f, cx, cy;           /* focal length and principal point in pixels */
+    float c2w[12];             /* row-major 3x4 [R | eye] */
+} cic_camera;
+
+/* Bytes of workspace needed by operation `op` for `n_items` rays (render_rays,
+ * render_backward) or pixels (the frame operations).  Returns 0 on invalid
+ * arguments. */
+size_t cic_workspace_bytes(int op, int64_t n_items, const cic_grid *grid, const cic_opts *opts);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *cic_last_error_message(void);
+
+/* Occupancy for empty-space skipping (the paper's Indexing stage finds the
+ * voxel of each sample, Sec. II-B; skipping empty voxels is the usual
+ * companion of dense-grid models).  occ[v] = 1 iff any of the voxel's eight
+ * vertices has softplus(raw + density_shift) > occ_sigma, evaluated as
+ * (raw + density_shift) > logf(expm1(occ_sigma)) in float32.  float32 grids
+ * only.  occ: device, (res0-1)(res1-1)(res2-1) bytes. */
+int build_occupancy(const cic_grid *grid, float occ_sigma, uint8_t *occ, cic_stream_t stream);
+
+/* One ray per pixel (Sec. II-B Indexing): origin = camera centre,
+ * direction = normalize(R * ((i+1/2-cx)/f, (j+1/2-cy)/f, 1)), in float32.
+ * pix: device int64 pixel indices [n], or NULL for all width*height pixels
+ * (then n must equal width*height).  rays_o, rays_d: device [n][3]. */
+int generate_rays(const cic_camera *cam, int64_t n, const int64_t *pix,
+                  float *rays_o, float *rays_d, cic_stream_t stream);
+
+/* Render a batch of rays: Indexing, Feature Gathering and Feature
+ * Computation of Sec. II-B, accumulated along each ray with the standard
+ * volume-rendering quadrature (Fig. 1 caption).  Per ray: slab interval
+ * [t_near, t_far] with the box, N samples at t_k = t_near + (k+1/2) delta,
+ * delta = (t_far - t_near)/N; sigma_k = softplus(trilerp(density) + shift);
+ * T_0 = 1, T_{k+1} = T_k exp(-sigma_k delta); w_k = T_k (1 - exp(-sigma_k delta));
+ * c_k = MLP(trilerp(features), direction); rgb = sum w_k c_k + T_stop bg;
+ * depth_t = sum w_k t_k; acc = 1 - T_stop.  With early termination the
+ * first sample with T_k < et_threshold and all later ones are dropped and
+ * T_stop is that T_k.  Skipped (unoccupied) voxels contribute sigma = 0.
+ * Missed rays give rgb = bg, depth_t = 0, acc = 0.
+ * opts->order = CIC_ORDER_VOXEL evaluates the MLP stage in voxel-bucket
+ * order (the memory-centric ordering of Sec. IV-A); results are identical to
+ * ray order.
+ * rgb [n][3], depth_t [n], acc [n]: device float32.  n_eval (device int64,
+ * nullable) is increased by the number of samples that went through the MLP. */
+int render_rays(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
+                const float *rays_o, const float *rays_d,
+                float *rgb, float *depth_t, float *acc, int64_t *n_eval,
+                void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* Render every pixel of a frame: generate_rays + render_rays, then the
+ * frame's z-depth depth_z = (depth_t/acc) * dot(d, camera forward) where
+ * acc >= void_acc, else +inf (the depth buffer SpaRW needs, Sec. III-B).
+ * rgb [H*W][3], depth_z [H*W], acc [H*W] (acc nullable). */
+int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cam,
+                 float *rgb, float *depth_z, float *acc, int64_t *n_eval,
+                 void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* SpaRW steps 1-3 (Sec. III-B, Eq. 1-3) in float32 without FMA contraction:
+ * each reference pixel with finite depth D becomes
+ * P = D ((i+1/2-cx)/f, (j+1/2-cy)/f, 1) (Eq. 1), P' = R P + t with
+ * ref_T_tgt = [R | t] (row-major 3x4, reference camera -> target camera,
+ * Eq. 2), and lands on target pixel (floor(u), floor(v)) with
+ * u = f_t X'/Z' + cx_t, v = f_t Y'/Z' + cy_t (Eq. 3) if Z' > 0 and inside the
+ * image.  A reference pixel with depth +inf is a direction: it is rotated
+ * only and carries depth +inf.  Each target pixel keeps the smallest depth,
+ * ties to the smallest reference pixel index (64-bit packed-key atomic min).
+ * Outputs (target size): tgt_rgb [H][W][3], tgt_depth_z [H][W] (+inf for
+ * directions, 0 where nothing landed), mask [H][W] u8 (1 = nothing landed,
+ * the disoccluded pixels to re-render), src_index [H][W] int32 (nullable;
+ * reference pixel or -1).  Reference rgb/depth: [Hr][Wr][3], [Hr][Wr]. */
+int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12],
+               const float *ref_rgb, const float *ref_depth_z,
+               float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
+               void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* SpaRW for one target frame (Sec. III-B, Eq. 4): warp_frame, then render the
+ * pixels of the mask (void pixels, those reached only by directions, are not
+ * re-rendered) with render_rays and put them in place of the warped values.
+ * out_rgb [H][W][3], out_depth_z [H][W], mask [H][W]; n_masked (device
+ * int64, nullable) receives the number of re-rendered pixels; n_eval as in
+ * render_rays.  Requires width*height <= 2^21 for the target. */
+int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
+                       const cic_camera *ref, const float *ref_rgb, const float *ref_depth_z,
+                       const cic_camera *tgt, const float ref_T_tgt[12],
+                       float *out_rgb, float *out_depth_z, uint8_t *mask,
+                       int64_t *n_masked, int64_t *n_eval,
+                       void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* Adjoint of render_rays (the derivative of the same quadrature; the paper
+ * itself is inference-only).  The forward is recomputed per ray; nothing
+ * from a previous forward call is needed.  Upstream gradients d_rgb [n][3],
+ * d_depth_t [n] (nullable), d_acc [n] (nullable).  Accumulates (+=) into
+ * d_density [res0][res1][res2], d_features [res0][res1][res2][12] and the
+ * MLP gradients shaped like the weights (all float32, device).  float32
+ * grids and CIC_F32 compute only. */
+int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
+                    const float *rays_o, const float *rays_d,
+                    const float *d_rgb, const float *d_depth_t, const float *d_acc,
+                    float *d_density, float *d_features,
+                    float *d_w0, float *d_b0, float *d_w1, float *d_b1, float *d_w2, float *d_b2,
+                    void *ws, size_t ws_bytes, cic_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CICERO_H */

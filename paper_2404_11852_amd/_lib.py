@@ -1,0 +1,227 @@
+"""ctypes binding of libcicero.so (argument marshalling only).
+
+Every function takes torch CUDA tensors, passes their device pointers and the
+current HIP stream to the C entry point of the same name, and raises on a
+non-zero return code.  No arithmetic of the method happens here; there is no
+CPU fallback: if the library is missing or the device is not gfx950 the
+calls raise.
+"""
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcicero.so")
+
+CIC_F32, CIC_F16, CIC_BF16 = 0, 1, 2
+CIC_ORDER_RAY, CIC_ORDER_VOXEL = 0, 1
+OP_RENDER_RAYS, OP_RENDER_FRAME, OP_WARP_FRAME, OP_RENDER_FRAME_SPARW, OP_RENDER_BACKWARD = range(5)
+
+
+class CicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("cicero error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("res", C.c_int32 * 3), ("n_feat", C.c_int32), ("storage", C.c_int32),
+                ("box_lo", C.c_float * 3), ("box_hi", C.c_float * 3), ("density_shift", C.c_float),
+                ("density", C.c_void_p), ("features", C.c_void_p), ("occupancy", C.c_void_p)]
+
+
+class MLP(C.Structure):
+    _fields_ = [("compute", C.c_int32), ("in_dim", C.c_int32), ("hidden", C.c_int32), ("pe_freqs", C.c_int32),
+                ("w0", C.c_void_p), ("b0", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_void_p),
+                ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("n_samples", C.c_int32), ("et_threshold", C.c_float), ("use_occupancy", C.c_int32),
+                ("bg", C.c_float * 3), ("void_acc", C.c_float), ("order", C.c_int32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("f", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("c2w", C.c_float * 12)]
+
+
+EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
+           "render_frame", "warp_frame", "render_frame_sparw", "render_backward"]
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libcicero.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise CicError(-3, "libcicero.so not built (run __graft_entry__.build())")
+                L = C.CDLL(LIB_PATH)
+                vp, i64, f, u64 = C.c_void_p, C.c_int64, C.c_float, C.c_size_t
+                L.cic_workspace_bytes.restype = u64
+                L.cic_workspace_bytes.argtypes = [C.c_int, i64, vp, vp]
+                L.cic_last_error_message.restype = C.c_char_p
+                L.cic_last_error_message.argtypes = []
+                L.build_occupancy.argtypes = [vp, f, vp, vp]
+                L.generate_rays.argtypes = [vp, i64, vp, vp, vp, vp]
+                L.render_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, u64, vp]
+                L.render_frame.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
+                L.warp_frame.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
+                L.render_frame_sparw.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
+                L.render_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                              vp, vp, u64, vp]
+                for name in EXPORTS[2:]:
+                    getattr(L, name).restype = C.c_int
+                _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().cic_last_error_message().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise CicError(rc, last_error())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# workspace: one growing byte buffer per device, reused across calls that run
+# on the same stream (calls sharing it must not overlap)
+# ---------------------------------------------------------------------------
+_ws = {}
+
+
+def workspace(nbytes, device):
+    key = torch.device(device).index or 0
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws[key] = None
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws[key] = buf
+    return buf
+
+
+def free_workspace():
+    _ws.clear()
+
+
+# ---------------------------------------------------------------------------
+# struct builders
+# ---------------------------------------------------------------------------
+def make_grid(density, features, occupancy=None, box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3, density_shift=0.0):
+    if density.dtype == torch.float32 and features.dtype == torch.float32:
+        storage = CIC_F32
+    elif density.dtype == torch.float16 and features.dtype == torch.float16:
+        storage = CIC_F16
+    else:
+        raise CicError(-1, "density/features must both be float32 or both float16")
+    if not (density.is_contiguous() and features.is_contiguous()):
+        raise CicError(-1, "grids must be contiguous")
+    g = Grid((C.c_int32 * 3)(*density.shape), int(features.shape[-1]), storage, (C.c_float * 3)(*box_lo),
+             (C.c_float * 3)(*box_hi), float(density_shift), density.data_ptr(), features.data_ptr(),
+             occupancy.data_ptr() if occupancy is not None else None)
+    g._keep = (density, features, occupancy)
+    return g
+
+
+def make_mlp(w, compute=CIC_F32):
+    ts = [w[k] for k in ("w0", "b0", "w1", "b1", "w2", "b2")]
+    for t in ts:
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise CicError(-1, "MLP weights must be contiguous float32")
+    hidden, in_dim = ts[0].shape
+    m = MLP(compute, int(in_dim), int(hidden), 4, *[t.data_ptr() for t in ts])
+    m._keep = ts
+    return m
+
+
+def make_opts(n_samples, et_threshold=0.0, use_occupancy=False, bg=(1.0, 1.0, 1.0), void_acc=1e-4,
+              order=CIC_ORDER_RAY):
+    return Opts(int(n_samples), float(et_threshold), int(bool(use_occupancy)), (C.c_float * 3)(*bg),
+                float(void_acc), int(order))
+
+
+def make_camera(width, height, f, cx, cy, c2w):
+    vals = [float(v) for v in torch.as_tensor(c2w, dtype=torch.float32).reshape(12).tolist()]
+    return Camera(int(width), int(height), float(f), float(cx), float(cy), (C.c_float * 12)(*vals))
+
+
+def workspace_bytes(op, n, grid=None, opts=None):
+    return int(lib().cic_workspace_bytes(op, int(n), C.byref(grid) if grid is not None else None,
+                                         C.byref(opts) if opts is not None else None))
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+def build_occupancy(grid, occ_sigma, occ):
+    _check(lib().build_occupancy(C.byref(grid), C.c_float(occ_sigma), _ptr(occ), _stream()))
+
+
+def generate_rays(cam, pix, rays_o, rays_d):
+    n = rays_o.shape[0]
+    _check(lib().generate_rays(C.byref(cam), C.c_int64(n), _ptr(pix), _ptr(rays_o), _ptr(rays_d), _stream()))
+
+
+def render_rays(grid, mlp, opts, rays_o, rays_d, rgb, depth_t, acc, n_eval=None):
+    n = rays_o.shape[0]
+    nb = workspace_bytes(OP_RENDER_RAYS, n, grid, opts)
+    ws = workspace(nb, rays_o.device)
+    _check(lib().render_rays(C.byref(grid), C.byref(mlp), C.byref(opts), C.c_int64(n), _ptr(rays_o),
+                             _ptr(rays_d), _ptr(rgb), _ptr(depth_t), _ptr(acc), _ptr(n_eval), _ptr(ws),
+                             C.c_size_t(ws.numel()), _stream()))
+
+
+def render_frame(grid, mlp, opts, cam, rgb, depth_z, acc=None, n_eval=None):
+    nb = workspace_bytes(OP_RENDER_FRAME, cam.width * cam.height, grid, opts)
+    ws = workspace(nb, rgb.device)
+    _check(lib().render_frame(C.byref(grid), C.byref(mlp), C.byref(opts), C.byref(cam), _ptr(rgb),
+                              _ptr(depth_z), _ptr(acc), _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()),
+                              _stream()))
+
+
+def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask, src_index=None):
+    nb = workspace_bytes(OP_WARP_FRAME, tgt_cam.width * tgt_cam.height)
+    ws = workspace(nb, ref_rgb.device)
+    Tc = (C.c_float * 12)(*[float(v) for v in torch.as_tensor(T, dtype=torch.float32).reshape(12).tolist()])
+    _check(lib().warp_frame(C.byref(ref_cam), C.byref(tgt_cam), Tc, _ptr(ref_rgb), _ptr(ref_depth),
+                            _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(src_index), _ptr(ws),
+                            C.c_size_t(ws.numel()), _stream()))
+
+
+def render_frame_sparw(grid, mlp, opts, ref_cam, ref_rgb, ref_depth, tgt_cam, T, out_rgb, out_depth, mask,
+                       n_masked=None, n_eval=None):
+    nb = workspace_bytes(OP_RENDER_FRAME_SPARW, tgt_cam.width * tgt_cam.height, grid, opts)
+    ws = workspace(nb, ref_rgb.device)
+    Tc = (C.c_float * 12)(*[float(v) for v in torch.as_tensor(T, dtype=torch.float32).reshape(12).tolist()])
+    _check(lib().render_frame_sparw(C.byref(grid), C.byref(mlp), C.byref(opts), C.byref(ref_cam), _ptr(ref_rgb),
+                                    _ptr(ref_depth), C.byref(tgt_cam), Tc, _ptr(out_rgb), _ptr(out_depth),
+                                    _ptr(mask), _ptr(n_masked), _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()),
+                                    _stream()))
+
+
+def render_backward(grid, mlp, opts, rays_o, rays_d, d_rgb, d_depth_t, d_acc, grads):
+    n = rays_o.shape[0]
+    nb = workspace_bytes(OP_RENDER_BACKWARD, n, grid, opts)
+    ws = workspace(nb, rays_o.device)
+    _check(lib().render_backward(C.byref(grid), C.byref(mlp), C.byref(opts), C.c_int64(n), _ptr(rays_o),
+                                 _ptr(rays_d), _ptr(d_rgb), _ptr(d_depth_t), _ptr(d_acc),
+                                 _ptr(grads["density"]), _ptr(grads["features"]), _ptr(grads["w0"]),
+                                 _ptr(grads["b0"]), _ptr(grads["w1"]), _ptr(grads["b1"]), _ptr(grads["w2"]),
+                                 _ptr(grads["b2"]), _ptr(ws), C.c_size_t(ws.numel()), _stream()))

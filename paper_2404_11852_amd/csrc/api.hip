@@ -1,0 +1,464 @@
+// C interface: argument validation, workspace carving and the launch
+// sequences of each entry point (see include/cicero.h for the contract).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <mutex>
+#include <string>
+
+#include "kernels.h"
+
+using namespace cic;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return CIC_OK;
+}
+
+// Workspace carving: 256-byte aligned sub-buffers from a base pointer; with
+// base == nullptr it only measures.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <typename T> T *take(int64_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += (size_t)(count > 0 ? count : 0) * sizeof(T);
+        return p;
+    }
+};
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+int check_grid(const cic_grid *g)
+{
+    if (!g) return fail(CIC_ERR_INVALID, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (g->res[a] < 2 || g->res[a] > 1024) return fail(CIC_ERR_INVALID, "grid.res[%d]=%d outside [2,1024]", a, g->res[a]);
+        if (!finite_f(g->box_lo[a]) || !finite_f(g->box_hi[a]) || !(g->box_hi[a] > g->box_lo[a]))
+            return fail(CIC_ERR_INVALID, "grid box axis %d is empty or not finite", a);
+    }
+    if (g->n_feat != 12) return fail(CIC_ERR_INVALID, "grid.n_feat=%d; only 12 channels are supported", g->n_feat);
+    if (g->storage != CIC_F32 && g->storage != CIC_F16)
+        return fail(CIC_ERR_INVALID, "grid.storage=%d; must be CIC_F32 or CIC_F16", g->storage);
+    if (!finite_f(g->density_shift)) return fail(CIC_ERR_INVALID, "grid.density_shift is not finite");
+    if (!g->density || !g->features) return fail(CIC_ERR_INVALID, "grid.density/features is NULL");
+    return CIC_OK;
+}
+
+int check_mlp(const cic_mlp *m)
+{
+    if (!m) return fail(CIC_ERR_INVALID, "mlp is NULL");
+    if (m->compute != CIC_F32) return fail(CIC_ERR_INVALID, "mlp.compute=%d is not supported", m->compute);
+    if (m->in_dim != 39 || m->hidden != 128 || m->pe_freqs != 4)
+        return fail(CIC_ERR_INVALID, "mlp shape in_dim=%d hidden=%d pe_freqs=%d; supported 39/128/4", m->in_dim,
+                    m->hidden, m->pe_freqs);
+    if (!m->w0 || !m->b0 || !m->w1 || !m->b1 || !m->w2 || !m->b2) return fail(CIC_ERR_INVALID, "mlp weight is NULL");
+    return CIC_OK;
+}
+
+int check_opts(const cic_opts *o, const cic_grid *g)
+{
+    if (!o) return fail(CIC_ERR_INVALID, "opts is NULL");
+    if (o->n_samples < 1 || o->n_samples > kMaxSamples)
+        return fail(CIC_ERR_INVALID, "opts.n_samples=%d outside [1,%d]", o->n_samples, kMaxSamples);
+    if (!finite_f(o->et_threshold) || o->et_threshold < 0.f || o->et_threshold >= 1.f)
+        return fail(CIC_ERR_INVALID, "opts.et_threshold must be in [0,1)");
+    if (o->use_occupancy && (!g || !g->occupancy))
+        return fail(CIC_ERR_INVALID, "opts.use_occupancy set but grid.occupancy is NULL");
+    if (o->order != CIC_ORDER_RAY && o->order != CIC_ORDER_VOXEL)
+        return fail(CIC_ERR_INVALID, "opts.order=%d is not CIC_ORDER_RAY/VOXEL", o->order);
+    for (int c = 0; c < 3; ++c)
+        if (!finite_f(o->bg[c])) return fail(CIC_ERR_INVALID, "opts.bg is not finite");
+    if (!finite_f(o->void_acc) || o->void_acc < 0.f) return fail(CIC_ERR_INVALID, "opts.void_acc must be >= 0");
+    return CIC_OK;
+}
+
+int check_camera(const cic_camera *c, const char *what)
+{
+    if (!c) return fail(CIC_ERR_INVALID, "%s camera is NULL", what);
+    if (c->width < 1 || c->width > 16384 || c->height < 1 || c->height > 16384)
+        return fail(CIC_ERR_INVALID, "%s camera size %dx%d outside [1,16384]", what, c->width, c->height);
+    if (!finite_f(c->f) || !(c->f > 0.f) || !finite_f(c->cx) || !finite_f(c->cy))
+        return fail(CIC_ERR_INVALID, "%s camera intrinsics invalid", what);
+    for (int i = 0; i < 12; ++i)
+        if (!finite_f(c->c2w[i])) return fail(CIC_ERR_INVALID, "%s camera pose is not finite", what);
+    return CIC_OK;
+}
+
+int64_t n_bricks_of(const cic_grid *g)
+{
+    int64_t nb = 1;
+    for (int a = 0; a < 3; ++a) nb *= (g->res[a] - 1 + kBrick - 1) / kBrick;
+    return nb;
+}
+
+GridK make_gridk(const cic_grid *g, bool use_occ)
+{
+    GridK k{};
+    k.r0 = g->res[0];
+    k.r1 = g->res[1];
+    k.r2 = g->res[2];
+    for (int a = 0; a < 3; ++a) {
+        k.lo[a] = g->box_lo[a];
+        k.hi[a] = g->box_hi[a];
+        k.scale[a] = (float)(g->res[a] - 1) / (g->box_hi[a] - g->box_lo[a]);
+    }
+    k.shift = g->density_shift;
+    k.density = g->density;
+    k.features = g->features;
+    k.occ = use_occ ? g->occupancy : nullptr;
+    k.nb1 = (g->res[1] - 1 + kBrick - 1) / kBrick;
+    k.nb2 = (g->res[2] - 1 + kBrick - 1) / kBrick;
+    return k;
+}
+
+OptsK make_optsk(const cic_opts *o)
+{
+    OptsK k{};
+    k.n_samples = o->n_samples;
+    k.et_threshold = o->et_threshold;
+    for (int c = 0; c < 3; ++c) k.bg[c] = o->bg[c];
+    k.void_acc = o->void_acc;
+    return k;
+}
+
+// Carve the buffers of one render pass of nc rays; generated rays live in
+// the workspace when gen_rays is set.
+RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool voxel, bool gen_rays)
+{
+    RenderBufs b{};
+    b.n = nc;
+    b.n_samples = N;
+    const int64_t ns = nc * (int64_t)N;
+    if (gen_rays) {
+        b.rays_o = cv.take<float>(3 * nc);
+        b.rays_d = cv.take<float>(3 * nc);
+    }
+    b.info = cv.take<RayInfo>(nc);
+    b.count = cv.take<uint32_t>(nc);
+    b.offsets = cv.take<uint32_t>(nc + 1);
+    b.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_elems(nc));
+    b.slot_k = cv.take<uint16_t>(ns);
+    b.slot_w = cv.take<float>(ns);
+    b.rec_ray = cv.take<uint32_t>(ns);
+    b.rec_k = cv.take<uint16_t>(ns);
+    b.rec_w = cv.take<float>(ns);
+    b.rec_c = cv.take<float>(3 * ns);
+    if (voxel) {
+        b.rec_key = cv.take<uint32_t>(ns);
+        b.brick_off = cv.take<uint32_t>(n_bricks + 1);
+        b.brick_tmp = cv.take<uint32_t>((int64_t)scan_tmp_elems(n_bricks));
+        b.perm = cv.take<uint32_t>(ns);
+    }
+    b.n_bricks = n_bricks;
+    return b;
+}
+
+struct WarpBufs {
+    uint64_t *zbuf;
+    int32_t *hole_idx;
+    uint32_t *n_holes;
+};
+
+WarpBufs carve_warp(Carver &cv, int64_t np, bool holes)
+{
+    WarpBufs w{};
+    w.zbuf = cv.take<uint64_t>(np);
+    if (holes) {
+        w.hole_idx = cv.take<int32_t>(np);
+        w.n_holes = cv.take<uint32_t>(1);
+    }
+    return w;
+}
+
+constexpr int64_t kChunkRaysBwd = 4096;
+
+size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
+{
+    Carver cv(nullptr);
+    const bool voxel = o->order == CIC_ORDER_VOXEL;
+    const int64_t nb = n_bricks_of(g);
+    switch (op) {
+    case CIC_OP_RENDER_RAYS: {
+        const int64_t nc = n < kChunkRays ? n : kChunkRays;
+        carve_render(cv, nc, o->n_samples, nb, voxel, false);
+        break;
+    }
+    case CIC_OP_RENDER_FRAME: {
+        const int64_t nc = n < kChunkRays ? n : kChunkRays;
+        carve_render(cv, nc, o->n_samples, nb, voxel, true);
+        break;
+    }
+    case CIC_OP_RENDER_FRAME_SPARW:
+        carve_warp(cv, n, true);
+        carve_render(cv, n, o->n_samples, nb, voxel, true);
+        break;
+    case CIC_OP_RENDER_BACKWARD: {
+        const int64_t nc = n < kChunkRaysBwd ? n : kChunkRaysBwd;
+        carve_render(cv, nc, o->n_samples, nb, voxel, false);
+        break;
+    }
+    default:
+        return 0;
+    }
+    return cv.off + 256;
+}
+
+// gfx950 check, once per device.
+std::mutex g_dev_mu;
+int g_dev_ok[64];   // 0 unknown, 1 ok, -1 not gfx950
+
+int check_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "no HIP device available");
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (dev >= 0 && dev < 64 && g_dev_ok[dev] == 0) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CIC_ERR_HIP, "hipGetDeviceProperties failed");
+        }
+        g_dev_ok[dev] = strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    }
+    if (dev < 0 || dev >= 64 || g_dev_ok[dev] != 1) return fail(CIC_ERR_DEVICE, "current device is not gfx950");
+    return CIC_OK;
+}
+
+int after_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CIC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+int check_ws(size_t need, void *ws, size_t ws_bytes)
+{
+    if (ws_bytes < need) return fail(CIC_ERR_WORKSPACE, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
+    if (need > 0 && !ws) return fail(CIC_ERR_INVALID, "workspace is NULL");
+    return CIC_OK;
+}
+
+void *align_ws(void *ws) { return (void *)(((uintptr_t)ws + 255) & ~(uintptr_t)255); }
+
+// Full render pipeline on one pass of rays.
+void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, const OptsK &ok_, bool voxel,
+                  RenderBufs &b, float *rgb, float *depth, float *acc, const int32_t *out_map,
+                  const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s)
+{
+    const bool f16 = grid->storage == CIC_F16;
+    if (f16) launch_march<__half>(gk, ok_, b, s);
+    else launch_march<float>(gk, ok_, b, s);
+    launch_exclusive_scan(b.count, b.offsets, b.scan_tmp, b.n, s);
+    if (voxel) launch_fill_u32(b.brick_off, 0u, b.n_bricks + 1, s);
+    launch_compact(gk, b, voxel, s);
+    if (voxel) {
+        launch_exclusive_scan(b.brick_off, b.brick_off, b.brick_tmp, b.n_bricks, s);
+        launch_brick_scatter(b, s);
+    }
+    if (f16) launch_mlp_forward<__half>(gk, *mlp, b, voxel, s);
+    else launch_mlp_forward<float>(gk, *mlp, b, voxel, s);
+    launch_reduce(b, ok_, rgb, depth, acc, out_map, frame_cam, n_eval, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cic_last_error_message(void) { return g_err.c_str(); }
+
+size_t cic_workspace_bytes(int op, int64_t n_items, const cic_grid *grid, const cic_opts *opts)
+{
+    if (n_items < 0) return 0;
+    if (op == CIC_OP_WARP_FRAME) {
+        Carver cv(nullptr);
+        carve_warp(cv, n_items, false);
+        return cv.off + 256;
+    }
+    if (check_grid(grid) != CIC_OK || check_opts(opts, grid) != CIC_OK) return 0;
+    return bytes_for(op, n_items, grid, opts);
+}
+
+int build_occupancy(const cic_grid *grid, float occ_sigma, uint8_t *occ, cic_stream_t stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!occ) return fail(CIC_ERR_INVALID, "occ is NULL");
+    if (!finite_f(occ_sigma) || !(occ_sigma > 0.f)) return fail(CIC_ERR_INVALID, "occ_sigma must be > 0");
+    if ((rc = check_device())) return rc;
+    const float thr = (float)std::log(std::expm1((double)occ_sigma));
+    GridK gk = make_gridk(grid, false);
+    if (grid->storage == CIC_F16) launch_build_occupancy<__half>(gk, thr, occ, (hipStream_t)stream);
+    else launch_build_occupancy<float>(gk, thr, occ, (hipStream_t)stream);
+    return after_launch("build_occupancy");
+}
+
+int generate_rays(const cic_camera *cam, int64_t n, const int64_t *pix, float *rays_o, float *rays_d,
+                  cic_stream_t stream)
+{
+    int rc = check_camera(cam, "");
+    if (rc) return rc;
+    if (n < 0) return fail(CIC_ERR_INVALID, "n < 0");
+    if (!pix && n != (int64_t)cam->width * cam->height)
+        return fail(CIC_ERR_INVALID, "pix is NULL but n != width*height");
+    if (n == 0) return ok();
+    if (!rays_o || !rays_d) return fail(CIC_ERR_INVALID, "rays_o/rays_d is NULL");
+    if ((rc = check_device())) return rc;
+    launch_generate_rays(*cam, n, 0, pix, nullptr, nullptr, rays_o, rays_d, (hipStream_t)stream);
+    return after_launch("generate_rays");
+}
+
+int render_rays(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays, const float *rays_o,
+                const float *rays_d, float *rgb, float *depth_t, float *acc, int64_t *n_eval, void *ws,
+                size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
+    if (n_rays < 0) return fail(CIC_ERR_INVALID, "n_rays < 0");
+    if (n_rays == 0) return ok();
+    if (!rays_o || !rays_d || !rgb || !depth_t || !acc) return fail(CIC_ERR_INVALID, "ray or output pointer is NULL");
+    const size_t need = bytes_for(CIC_OP_RENDER_RAYS, n_rays, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool voxel = opts->order == CIC_ORDER_VOXEL;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    const int64_t nb = n_bricks_of(grid);
+    for (int64_t c0 = 0; c0 < n_rays; c0 += kChunkRays) {
+        const int64_t nc = (n_rays - c0) < kChunkRays ? (n_rays - c0) : kChunkRays;
+        Carver cv(align_ws(ws));
+        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, false);
+        b.rays_o = rays_o + 3 * c0;
+        b.rays_d = rays_d + 3 * c0;
+        run_pipeline(grid, gk, mlp, ok_, voxel, b, rgb + 3 * c0, depth_t + c0, acc + c0, nullptr, nullptr, n_eval,
+                     s);
+    }
+    return after_launch("render_rays");
+}
+
+int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cam, float *rgb,
+                 float *depth_z, float *acc, int64_t *n_eval, void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid)) ||
+        (rc = check_camera(cam, "")))
+        return rc;
+    if (!rgb || !depth_z) return fail(CIC_ERR_INVALID, "rgb/depth_z is NULL");
+    const int64_t np = (int64_t)cam->width * cam->height;
+    const size_t need = bytes_for(CIC_OP_RENDER_FRAME, np, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool voxel = opts->order == CIC_ORDER_VOXEL;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    const int64_t nb = n_bricks_of(grid);
+    for (int64_t c0 = 0; c0 < np; c0 += kChunkRays) {
+        const int64_t nc = (np - c0) < kChunkRays ? (np - c0) : kChunkRays;
+        Carver cv(align_ws(ws));
+        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, true);
+        launch_generate_rays(*cam, nc, c0, nullptr, nullptr, nullptr, (float *)b.rays_o, (float *)b.rays_d, s);
+        run_pipeline(grid, gk, mlp, ok_, voxel, b, rgb + 3 * c0, depth_z + c0, acc ? acc + c0 : nullptr, nullptr,
+                     cam, n_eval, s);
+    }
+    return after_launch("render_frame");
+}
+
+int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12], const float *ref_rgb,
+               const float *ref_depth_z, float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
+               void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_camera(ref, "reference")) || (rc = check_camera(tgt, "target"))) return rc;
+    if (!ref_T_tgt) return fail(CIC_ERR_INVALID, "ref_T_tgt is NULL");
+    for (int i = 0; i < 12; ++i)
+        if (!finite_f(ref_T_tgt[i])) return fail(CIC_ERR_INVALID, "ref_T_tgt is not finite");
+    if ((int64_t)ref->width * ref->height > 0xffffffffll) return fail(CIC_ERR_INVALID, "reference too large");
+    if (!ref_rgb || !ref_depth_z || !tgt_rgb || !tgt_depth_z || !mask)
+        return fail(CIC_ERR_INVALID, "frame pointer is NULL");
+    const int64_t np = (int64_t)tgt->width * tgt->height;
+    Carver m(nullptr);
+    carve_warp(m, np, false);
+    const size_t need = m.off + 256;
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    Carver cv(align_ws(ws));
+    WarpBufs w = carve_warp(cv, np, false);
+    launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, tgt_rgb, tgt_depth_z, mask, src_index, nullptr,
+                nullptr, (hipStream_t)stream);
+    return after_launch("warp_frame");
+}
+
+int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *ref,
+                       const float *ref_rgb, const float *ref_depth_z, const cic_camera *tgt,
+                       const float ref_T_tgt[12], float *out_rgb, float *out_depth_z, uint8_t *mask,
+                       int64_t *n_masked, int64_t *n_eval, void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid)) ||
+        (rc = check_camera(ref, "reference")) || (rc = check_camera(tgt, "target")))
+        return rc;
+    if (!ref_T_tgt) return fail(CIC_ERR_INVALID, "ref_T_tgt is NULL");
+    for (int i = 0; i < 12; ++i)
+        if (!finite_f(ref_T_tgt[i])) return fail(CIC_ERR_INVALID, "ref_T_tgt is not finite");
+    if (!ref_rgb || !ref_depth_z || !out_rgb || !out_depth_z || !mask)
+        return fail(CIC_ERR_INVALID, "frame pointer is NULL");
+    const int64_t np = (int64_t)tgt->width * tgt->height;
+    if (np > kChunkRays) return fail(CIC_ERR_INVALID, "target frame has %lld pixels; at most %lld", (long long)np,
+                                     (long long)kChunkRays);
+    const size_t need = bytes_for(CIC_OP_RENDER_FRAME_SPARW, np, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool voxel = opts->order == CIC_ORDER_VOXEL;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    Carver cv(align_ws(ws));
+    WarpBufs w = carve_warp(cv, np, true);
+    RenderBufs b = carve_render(cv, np, opts->n_samples, n_bricks_of(grid), voxel, true);
+    b.n_active = w.n_holes;
+    launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, out_rgb, out_depth_z, mask, nullptr,
+                w.hole_idx, w.n_holes, s);
+    launch_generate_rays(*tgt, np, 0, nullptr, w.hole_idx, w.n_holes, (float *)b.rays_o, (float *)b.rays_d, s);
+    run_pipeline(grid, gk, mlp, ok_, voxel, b, out_rgb, out_depth_z, nullptr, w.hole_idx, tgt, n_eval, s);
+    if (n_masked) launch_sparw_finish(w.n_holes, n_masked, s);
+    return after_launch("render_frame_sparw");
+}
+
+int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
+                    const float *rays_o, const float *rays_d, const float *d_rgb, const float *d_depth_t,
+                    const float *d_acc, float *d_density, float *d_features, float *d_w0, float *d_b0, float *d_w1,
+                    float *d_b1, float *d_w2, float *d_b2, void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    (void)grid; (void)mlp; (void)opts; (void)n_rays; (void)rays_o; (void)rays_d; (void)d_rgb; (void)d_depth_t;
+    (void)d_acc; (void)d_density; (void)d_features; (void)d_w0; (void)d_b0; (void)d_w1; (void)d_b1; (void)d_w2;
+    (void)d_b2; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(CIC_ERR_INVALID, "render_backward is not available in this build");
+}
+
+}  // extern "C"

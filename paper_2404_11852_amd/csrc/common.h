@@ -1,0 +1,190 @@
+// Device-side building blocks shared by the renderer's kernels (gfx950,
+// wave64).  Whole library is compiled with -ffp-contract=off so that the
+// float32 geometry below (ray/box interval, sample positions, voxel index,
+// warp projection) rounds exactly as written; arithmetic that may fuse uses
+// fmaf explicitly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "cicero.h"
+
+namespace cic {
+
+constexpr int kWave = 64;
+constexpr int kBrick = 8;            // voxels per brick edge (voxel-order bucketing)
+constexpr int kMaxSamples = 1024;    // samples per ray
+constexpr int64_t kChunkRays = 1 << 21;  // rays per pipeline pass
+
+// Grid description as the kernels see it (filled on the host).
+struct GridK {
+    int r0, r1, r2;        // vertices per axis
+    float lo[3], hi[3];
+    float scale[3];        // (r-1)/(hi-lo) per axis, float32 as computed on the host
+    float shift;           // density shift before softplus
+    const void *density;
+    const void *features;
+    const uint8_t *occ;    // nullptr when skipping is off
+    int nb1, nb2;          // bricks along axes 1 and 2
+};
+
+struct OptsK {
+    int n_samples;
+    float et_threshold;
+    float bg[3];
+    float void_acc;
+};
+
+// --------------------------------------------------------------------------
+// storage loads
+// --------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ float ldv(const T *p, int64_t i);
+template <> __device__ __forceinline__ float ldv<float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ldv<__half>(const __half *p, int64_t i) { return __half2float(p[i]); }
+
+// --------------------------------------------------------------------------
+// float32 geometry (decides integers; written in the same expression order
+// as the reference description, no contraction)
+// --------------------------------------------------------------------------
+
+// Slab test against the box: 0 <= t_near < t_far on a hit.
+__device__ __forceinline__ bool ray_box(const float o[3], const float d[3], const GridK &g, float &tn, float &tf)
+{
+    float a = -INFINITY, b = INFINITY;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float inv = 1.0f / d[k];
+        float t0 = (g.lo[k] - o[k]) * inv;
+        float t1 = (g.hi[k] - o[k]) * inv;
+        a = fmaxf(a, fminf(t0, t1));
+        b = fminf(b, fmaxf(t0, t1));
+    }
+    a = fmaxf(a, 0.0f);
+    tn = a;
+    tf = b;
+    return a < b;
+}
+
+// Sample k of a ray: t_k = t_near + (k + 1/2) delta, x = o + t_k d.
+__device__ __forceinline__ float sample_t(float tn, float delta, int k)
+{
+    return tn + ((float)k + 0.5f) * delta;
+}
+
+// World position -> lower vertex index of the voxel and fraction inside it.
+__device__ __forceinline__ void locate(const float x[3], const GridK &g, int i0[3], float fr[3])
+{
+    const int rr[3] = {g.r0, g.r1, g.r2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float u = (x[k] - g.lo[k]) * g.scale[k];
+        int i = (int)floorf(u);
+        i = i < 0 ? 0 : i;
+        i = i > rr[k] - 2 ? rr[k] - 2 : i;
+        float f = u - (float)i;
+        fr[k] = fminf(fmaxf(f, 0.0f), 1.0f);
+        i0[k] = i;
+    }
+}
+
+__device__ __forceinline__ int64_t cell_index(const GridK &g, const int i0[3])
+{
+    return ((int64_t)i0[0] * (g.r1 - 1) + i0[1]) * (int64_t)(g.r2 - 1) + i0[2];
+}
+
+__device__ __forceinline__ int64_t vertex_index(const GridK &g, int x, int y, int z)
+{
+    return ((int64_t)x * g.r1 + y) * (int64_t)g.r2 + z;
+}
+
+__device__ __forceinline__ uint32_t brick_of(const GridK &g, const int i0[3])
+{
+    return ((uint32_t)(i0[0] / kBrick) * g.nb1 + (uint32_t)(i0[1] / kBrick)) * g.nb2 + (uint32_t)(i0[2] / kBrick);
+}
+
+// Recompute the voxel of sample k of a ray (bit-identical to the march).
+__device__ __forceinline__ void sample_voxel(const float o[3], const float d[3], float tn, float delta, int k,
+                                             const GridK &g, int i0[3], float fr[3], float &tk)
+{
+    tk = sample_t(tn, delta, k);
+    float x[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = o[a] + tk * d[a];
+    locate(x, g, i0, fr);
+}
+
+// Pixel ray in float32 (centre of pixel (i, j), pinhole camera).
+__device__ __forceinline__ void pixel_ray(const cic_camera &c, int i, int j, float o[3], float d[3])
+{
+    float a = (((float)i + 0.5f) - c.cx) / c.f;
+    float b = (((float)j + 0.5f) - c.cy) / c.f;
+    float dx = (c.c2w[0] * a + c.c2w[1] * b) + c.c2w[2];
+    float dy = (c.c2w[4] * a + c.c2w[5] * b) + c.c2w[6];
+    float dz = (c.c2w[8] * a + c.c2w[9] * b) + c.c2w[10];
+    float n = sqrtf((dx * dx + dy * dy) + dz * dz);
+    d[0] = dx / n;
+    d[1] = dy / n;
+    d[2] = dz / n;
+    o[0] = c.c2w[3];
+    o[1] = c.c2w[7];
+    o[2] = c.c2w[11];
+}
+
+// --------------------------------------------------------------------------
+// float32 arithmetic
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Trilinear interpolation of one scalar channel (stride = channels per vertex).
+template <typename T>
+__device__ __forceinline__ float trilerp1(const T *v, const GridK &g, const int i0[3], const float fr[3], int stride,
+                                          int ch)
+{
+    const int64_t sx = (int64_t)g.r1 * g.r2 * stride, sy = (int64_t)g.r2 * stride, sz = stride;
+    const int64_t b = vertex_index(g, i0[0], i0[1], i0[2]) * stride + ch;
+    float v000 = ldv(v, b), v001 = ldv(v, b + sz), v010 = ldv(v, b + sy), v011 = ldv(v, b + sy + sz);
+    float v100 = ldv(v, b + sx), v101 = ldv(v, b + sx + sz), v110 = ldv(v, b + sx + sy),
+          v111 = ldv(v, b + sx + sy + sz);
+    float c00 = lerpf(v000, v001, fr[2]), c01 = lerpf(v010, v011, fr[2]);
+    float c10 = lerpf(v100, v101, fr[2]), c11 = lerpf(v110, v111, fr[2]);
+    float c0 = lerpf(c00, c01, fr[1]), c1 = lerpf(c10, c11, fr[1]);
+    return lerpf(c0, c1, fr[0]);
+}
+
+__device__ __forceinline__ float softplusf(float x)
+{
+    return x > 15.0f ? x + expf(-x) : log1pf(expf(x));
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// --------------------------------------------------------------------------
+// wavefront primitives
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Inclusive prefix sum across the 64 lanes (Hillis-Steele).
+__device__ __forceinline__ float wave_incl_scan(float v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        float u = __shfl_up(v, off, kWave);
+        if (l >= off) v += u;
+    }
+    return v;
+}
+
+// Sum across the wave; every lane gets the identical value.
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanes_below_mask() { return (1ull << lane_id()) - 1ull; }
+
+}  // namespace cic

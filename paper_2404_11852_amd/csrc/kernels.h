@@ -1,0 +1,93 @@
+// Host-side launchers of the renderer's kernels (one translation unit per
+// group of kernels; the C interface in api.hip strings them together).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace cic {
+
+// Per-ray state written by the march: t_near, delta, T_stop, sum w_k t_k.
+struct RayInfo {
+    float tn, delta, t_stop, depth_t;
+};
+
+// Device buffers of one render pass (carved from the caller's workspace).
+struct RenderBufs {
+    int64_t n;             // rays in this pass (upper bound when n_active is set)
+    int n_samples;
+    const float *rays_o, *rays_d;
+    const uint32_t *n_active;  // device count of active rays (nullable)
+    RayInfo *info;
+    uint32_t *count;       // [n] live samples per ray
+    uint32_t *offsets;     // [n+1] exclusive scan of count
+    uint32_t *scan_tmp;    // block sums
+    uint16_t *slot_k;      // [n*N] live sample indices, per-ray fixed slots
+    float *slot_w;         // [n*N] their weights
+    uint32_t *rec_ray;     // [n*N] compacted: ray of each live sample
+    uint16_t *rec_k;       // [n*N] its sample index
+    float *rec_w;          // [n*N] its weight
+    float *rec_c;          // [n*N*3] MLP colour per live sample
+    // voxel order
+    uint32_t *rec_key;     // [n*N] brick of each live sample
+    uint32_t *brick_off;   // [n_bricks+1] counts, then cursors
+    uint32_t *brick_tmp;   // block sums for the brick scan
+    uint32_t *perm;        // [n*N] sample order for the MLP stage
+    int64_t n_bricks;
+};
+
+// scan.hip
+size_t scan_tmp_elems(int64_t n);
+void launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t *tmp, int64_t n, hipStream_t s);
+
+// render.hip
+template <typename T>
+void launch_march(const GridK &g, const OptsK &o, const RenderBufs &b, hipStream_t s);
+void launch_compact(const GridK &g, const RenderBufs &b, bool voxel_keys, hipStream_t s);
+void launch_brick_scatter(const RenderBufs &b, hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+// Final per-ray accumulation.  out_map (nullable) maps ray -> output slot;
+// frame_cam (nullable) switches depth output to frame z-depth.
+void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,
+                   const int32_t *out_map, const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s);
+void launch_generate_rays(const cic_camera &cam, int64_t n, int64_t base, const int64_t *pix, const int32_t *pix32,
+                          const uint32_t *n_active, float *o, float *d, hipStream_t s);
+template <typename T>
+void launch_build_occupancy(const GridK &g, float thr, uint8_t *occ, hipStream_t s);
+
+// mlp.hip
+int mlp_lds_bytes(int compute);
+template <typename T>
+void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
+
+// warp.hip
+void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], const float *ref_rgb,
+                 const float *ref_depth, uint64_t *zbuf, float *tgt_rgb, float *tgt_depth, uint8_t *mask,
+                 int32_t *src_index, int32_t *hole_idx, uint32_t *n_holes, hipStream_t s);
+void launch_sparw_finish(const uint32_t *n_holes, int64_t *n_masked, hipStream_t s);
+
+// backward.hip
+struct BackwardBufs {
+    const float *d_rgb, *d_depth_t, *d_acc;
+    float *d_density, *d_features;
+    float *d_w0, *d_b0, *d_w1, *d_b1, *d_w2, *d_b2;
+    float *rec_dc;         // [n*N*3] dL/dc per live sample
+    float *stage;          // [n*N][kStageStride] per-sample vectors for the weight gradients
+    float *partials;       // [n_part][kParamCount] per-block weight-gradient partials
+    int64_t n_part_max;
+};
+constexpr int kStageX = 40, kStageH = 128;
+constexpr int kStageStride = kStageX + 4 * kStageH + 4;   // x | h1 | h2 | dp0 | dp1 | dlogit
+constexpr int kParamCount = 128 * 39 + 128 + 128 * 128 + 128 + 3 * 128 + 3;
+template <typename T>
+void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
+                               hipStream_t s);
+template <typename T>
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb,
+                         hipStream_t s);
+void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
+
+}  // namespace cic

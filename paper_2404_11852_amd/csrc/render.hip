@@ -1,0 +1,346 @@
+// Ray marching, live-sample compaction, voxel-order bucketing and the final
+// per-ray accumulation of the rendering quadrature.
+//
+// March: one wavefront per ray, 64 samples per step (one per lane).  Each
+// lane finds its sample's voxel, skips it if unoccupied, interpolates the
+// raw density, applies softplus and forms the optical depth sigma*delta.  A
+// wavefront inclusive scan of the optical depths gives every lane its
+// transmittance T_k = exp(-(carry + exclusive sum)); the first lane whose
+// T_k falls below the threshold ends the ray (ballot + find-first-set).
+// Live samples (occupied, before termination) are written to per-ray slots
+// with their weight w_k = T_k (1 - exp(-sigma_k delta)); sum w_k t_k is a
+// wavefront tree sum.  The MLP stage later reads the compacted live samples;
+// the per-ray reduction sums w_k c_k in sample order, so results do not
+// depend on the order in which the MLP stage visits samples.
+#include "kernels.h"
+
+namespace cic {
+
+constexpr int kRayWaves = 4;   // rays (wavefronts) per 256-thread block
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
+{
+    const int lane = lane_id();
+    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
+    if (ray >= b.n) return;
+    const uint32_t n_act = b.n_active ? *b.n_active : (uint32_t)b.n;
+    if ((uint64_t)ray >= n_act) {
+        if (lane == 0) {
+            b.count[ray] = 0;
+            b.info[ray] = RayInfo{0.f, 0.f, 1.f, 0.f};
+        }
+        return;
+    }
+    float o[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[a] = b.rays_o[3 * ray + a];
+        d[a] = b.rays_d[3 * ray + a];
+    }
+    float tn, tf;
+    if (!ray_box(o, d, g, tn, tf)) {
+        if (lane == 0) {
+            b.count[ray] = 0;
+            b.info[ray] = RayInfo{tn, 0.f, 1.f, 0.f};
+        }
+        return;
+    }
+    const int N = op.n_samples;
+    const float delta = (tf - tn) / (float)N;
+    const float thr = op.et_threshold;
+    const T *dens = (const T *)g.density;
+    uint16_t *slot_k = b.slot_k + ray * (int64_t)N;
+    float *slot_w = b.slot_w + ray * (int64_t)N;
+    float carry = 0.f, depth = 0.f, t_stop = -1.f;
+    uint32_t count = 0;
+    for (int base = 0; base < N; base += kWave) {
+        const int k = base + lane;
+        const bool valid = k < N;
+        float s = 0.f, tk = 0.f;
+        bool occ = false;
+        if (valid) {
+            int i0[3];
+            float fr[3];
+            sample_voxel(o, d, tn, delta, k, g, i0, fr, tk);
+            occ = g.occ ? (g.occ[cell_index(g, i0)] != 0) : true;
+            if (occ) {
+                float raw = trilerp1(dens, g, i0, fr, 1, 0);
+                s = softplusf(raw + g.shift) * delta;
+            }
+        }
+        const float incl = wave_incl_scan(s);
+        float excl = __shfl_up(incl, 1, kWave);
+        if (lane == 0) excl = 0.f;
+        const float Tk = expf(-(carry + excl));
+        const bool term = valid && thr > 0.f && Tk < thr;
+        const uint64_t tmask = __ballot(term);
+        const int first = tmask ? (__ffsll((unsigned long long)tmask) - 1) : kWave;
+        const bool live = valid && occ && lane < first;
+        const float w = live ? Tk * (-expm1f(-s)) : 0.f;
+        const uint64_t lmask = __ballot(live);
+        if (live) {
+            const uint32_t pos = count + (uint32_t)__popcll(lmask & lanes_below_mask());
+            slot_k[pos] = (uint16_t)k;
+            slot_w[pos] = w;
+        }
+        count += (uint32_t)__popcll(lmask);
+        depth += wave_sum(w * tk);
+        if (first < kWave) {
+            t_stop = __shfl(Tk, first, kWave);
+            break;
+        }
+        carry += __shfl(incl, kWave - 1, kWave);
+    }
+    if (t_stop < 0.f) t_stop = expf(-carry);
+    if (lane == 0) {
+        b.count[ray] = count;
+        b.info[ray] = RayInfo{tn, delta, t_stop, depth};
+    }
+}
+
+template <typename T>
+void launch_march(const GridK &g, const OptsK &o, const RenderBufs &b, hipStream_t s)
+{
+    if (b.n == 0) return;
+    const unsigned blocks = (unsigned)((b.n + kRayWaves - 1) / kRayWaves);
+    hipLaunchKernelGGL(k_march<T>, dim3(blocks), dim3(256), 0, s, g, o, b);
+}
+template void launch_march<float>(const GridK &, const OptsK &, const RenderBufs &, hipStream_t);
+template void launch_march<__half>(const GridK &, const OptsK &, const RenderBufs &, hipStream_t);
+
+// Head-of-run detection for equal consecutive keys among the first `active`
+// lanes: returns the mask of run heads; run length of a head lane is the
+// distance to the next head (or to `active`).
+__device__ __forceinline__ uint64_t run_heads(uint32_t key, bool active)
+{
+    const uint32_t prev = __shfl_up(key, 1, kWave);
+    const bool head = active && (lane_id() == 0 || prev != key);
+    return __ballot(head);
+}
+
+__device__ __forceinline__ int run_length(uint64_t heads, int active)
+{
+    const int l = lane_id();
+    const uint64_t above = (l == kWave - 1) ? 0ull : (heads & ~((2ull << l) - 1ull));
+    const int next = above ? (__ffsll((unsigned long long)above) - 1) : active;
+    return next - l;
+}
+
+// One wavefront per ray copies its live samples to their compacted position
+// (ray-order), and in voxel mode tags each with its brick and counts bricks.
+__global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxel)
+{
+    const int lane = lane_id();
+    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
+    if (ray >= b.n) return;
+    const uint32_t cnt = b.count[ray];
+    if (cnt == 0) return;
+    const uint32_t off = b.offsets[ray];
+    const int N = b.n_samples;
+    float o[3], d[3];
+    RayInfo inf;
+    if (voxel) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = b.rays_o[3 * ray + a];
+            d[a] = b.rays_d[3 * ray + a];
+        }
+        inf = b.info[ray];
+    }
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+        const uint32_t j = j0 + lane;
+        const bool act = j < cnt;
+        uint32_t key = 0xffffffffu;
+        if (act) {
+            const uint16_t k = b.slot_k[ray * (int64_t)N + j];
+            b.rec_ray[off + j] = (uint32_t)ray;
+            b.rec_k[off + j] = k;
+            b.rec_w[off + j] = b.slot_w[ray * (int64_t)N + j];
+            if (voxel) {
+                int i0[3];
+                float fr[3], tk;
+                sample_voxel(o, d, inf.tn, inf.delta, k, g, i0, fr, tk);
+                key = brick_of(g, i0);
+                b.rec_key[off + j] = key;
+            }
+        }
+        if (voxel) {
+            const int active = (int)min(cnt - j0, (uint32_t)kWave);
+            const uint64_t heads = run_heads(key, act);
+            if ((heads >> lane) & 1ull) atomicAdd(&b.brick_off[key], (uint32_t)run_length(heads, active));
+        }
+    }
+}
+
+void launch_compact(const GridK &g, const RenderBufs &b, bool voxel_keys, hipStream_t s)
+{
+    if (b.n == 0) return;
+    const unsigned blocks = (unsigned)((b.n + kRayWaves - 1) / kRayWaves);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, g, b, voxel_keys ? 1 : 0);
+}
+
+// Bucket scatter: brick_off holds the exclusive scan of brick counts and is
+// advanced as a cursor; each run of equal bricks takes one atomic.
+__global__ __launch_bounds__(256) void k_brick_scatter(RenderBufs b)
+{
+    const int lane = lane_id();
+    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
+    if (ray >= b.n) return;
+    const uint32_t cnt = b.count[ray];
+    if (cnt == 0) return;
+    const uint32_t off = b.offsets[ray];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+        const uint32_t j = j0 + lane;
+        const bool act = j < cnt;
+        const uint32_t key = act ? b.rec_key[off + j] : 0xffffffffu;
+        const int active = (int)min(cnt - j0, (uint32_t)kWave);
+        const uint64_t heads = run_heads(key, act);
+        uint32_t base = 0;
+        if ((heads >> lane) & 1ull) base = atomicAdd(&b.brick_off[key], (uint32_t)run_length(heads, active));
+        // head of my run = highest head at or below my lane
+        const uint64_t upto = heads & ((lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1ull));
+        const int head = upto ? (63 - __clzll((long long)upto)) : 0;
+        const uint32_t hb = __shfl(base, head, kWave);
+        if (act) b.perm[hb + (uint32_t)(lane - head)] = off + j;
+    }
+}
+
+void launch_brick_scatter(const RenderBufs &b, hipStream_t s)
+{
+    if (b.n == 0) return;
+    const unsigned blocks = (unsigned)((b.n + kRayWaves - 1) / kRayWaves);
+    hipLaunchKernelGGL(k_brick_scatter, dim3(blocks), dim3(256), 0, s, b);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+static unsigned fill_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+
+// Per-ray accumulation: rgb = sum_k w_k c_k (in sample order) + T_stop bg,
+// depth_t, acc = 1 - T_stop; frame mode converts to z-depth with the void
+// rule.  One thread per ray.
+__global__ __launch_bounds__(256) void k_reduce(RenderBufs b, OptsK op, float *rgb, float *depth, float *acc,
+                                                const int32_t *out_map, cic_camera cam, int frame,
+                                                unsigned long long *n_eval)
+{
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_act = b.n_active ? *b.n_active : (uint32_t)b.n;
+    if (n_eval && ray == 0) atomicAdd(n_eval, (unsigned long long)b.offsets[b.n]);
+    if (ray >= b.n || (uint64_t)ray >= n_act) return;
+    const uint32_t cnt = b.count[ray], off = b.offsets[ray];
+    const RayInfo inf = b.info[ray];
+    float r = 0.f, gg = 0.f, bb = 0.f;
+    for (uint32_t j = 0; j < cnt; ++j) {
+        const float w = b.rec_w[off + j];
+        const float *c = b.rec_c + 3 * (int64_t)(off + j);
+        r = fmaf(w, c[0], r);
+        gg = fmaf(w, c[1], gg);
+        bb = fmaf(w, c[2], bb);
+    }
+    const float ts = inf.t_stop;
+    const int64_t out = out_map ? (int64_t)out_map[ray] : ray;
+    rgb[3 * out + 0] = fmaf(ts, op.bg[0], r);
+    rgb[3 * out + 1] = fmaf(ts, op.bg[1], gg);
+    rgb[3 * out + 2] = fmaf(ts, op.bg[2], bb);
+    const float a = 1.0f - ts;
+    if (acc) acc[out] = a;
+    if (frame) {
+        float dz = INFINITY;
+        if (a >= op.void_acc) {
+            const float *d = b.rays_d + 3 * ray;
+            const float cosang = fmaf(d[0], cam.c2w[2], fmaf(d[1], cam.c2w[6], d[2] * cam.c2w[10]));
+            dz = inf.depth_t / a * cosang;
+        }
+        depth[out] = dz;
+    } else {
+        depth[out] = inf.depth_t;
+    }
+}
+
+void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,
+                   const int32_t *out_map, const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s)
+{
+    const int64_t blocks = (b.n + 255) / 256;
+    cic_camera cam{};
+    if (frame_cam) cam = *frame_cam;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, b, o, rgb, depth, acc,
+                       out_map, cam, frame_cam ? 1 : 0, (unsigned long long *)n_eval);
+}
+
+// Pixel rays; pixel index from pix (int64), pix32 (int32) or identity.
+__global__ __launch_bounds__(256) void k_generate_rays(cic_camera cam, int64_t n, int64_t base, const int64_t *pix,
+                                                       const int32_t *pix32, const uint32_t *n_active, float *o,
+                                                       float *d)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (n_active && (uint64_t)r >= *n_active) return;
+    const int64_t p = pix ? pix[r] : (pix32 ? (int64_t)pix32[r] : base + r);
+    float oo[3], dd[3];
+    pixel_ray(cam, (int)(p % cam.width), (int)(p / cam.width), oo, dd);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[3 * r + a] = oo[a];
+        d[3 * r + a] = dd[a];
+    }
+}
+
+void launch_generate_rays(const cic_camera &cam, int64_t n, int64_t base, const int64_t *pix, const int32_t *pix32,
+                          const uint32_t *n_active, float *o, float *d, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_generate_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cam, n, base, pix, pix32,
+                       n_active, o, d);
+}
+
+// Occupancy: a voxel is occupied iff any vertex has raw + shift > thr
+// (thr = log(expm1(occ_sigma)) rounded to float32 on the host).
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_occupancy(GridK g, float thr, uint8_t *occ)
+{
+    const int64_t c1 = g.r1 - 1, c2 = g.r2 - 1;
+    const int64_t nc = (int64_t)(g.r0 - 1) * c1 * c2;
+    const T *dens = (const T *)g.density;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(c / (c1 * c2)), y = (int)((c / c2) % c1), z = (int)(c % c2);
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const float s = ldv(dens, vertex_index(g, x + ((v >> 2) & 1), y + ((v >> 1) & 1), z + (v & 1))) + g.shift;
+            any |= s > thr;
+        }
+        occ[c] = any ? 1 : 0;
+    }
+}
+
+template <typename T>
+void launch_build_occupancy(const GridK &g, float thr, uint8_t *occ, hipStream_t s)
+{
+    const int64_t nc = (int64_t)(g.r0 - 1) * (g.r1 - 1) * (g.r2 - 1);
+    hipLaunchKernelGGL(k_build_occupancy<T>, dim3(fill_blocks(nc)), dim3(256), 0, s, g, thr, occ);
+}
+template void launch_build_occupancy<float>(const GridK &, float, uint8_t *, hipStream_t);
+template void launch_build_occupancy<__half>(const GridK &, float, uint8_t *, hipStream_t);
+
+}  // namespace cic

@@ -1,0 +1,184 @@
+"""GPU parity of the forward path (ray generation, occupancy, rendering)
+against the float64 oracle, through the C interface."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import BG, Pair, cams, compare, print_case, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import paper_2404_11852_amd as cic
+    cic._lib.lib()   # raises if the library is missing: no fallback
+    assert torch.cuda.is_available()
+    yield
+    cic._lib.free_workspace()
+
+
+@pytest.mark.parametrize("W,H,k", [(64, 64, 0), (37, 23, 9), (800, 800, 3)])
+def test_generate_rays_bit_exact(W, H, k):
+    import paper_2404_11852_amd as cic
+    print_case("generate_rays %dx%d pose %d" % (W, H, k))
+    gc, oc = cams(W, H, synth.orbit_pose(k))
+    o, d = cic.generate_rays(gc)
+    oo, od = oracle.generate_rays(oc)
+    assert np.array_equal(to_np(o), oo)
+    assert np.array_equal(to_np(d), od)
+    pix = synth.pixel_subset(W, H, min(500, W * H), seed=4)
+    o2, d2 = cic.generate_rays(gc, torch.from_numpy(pix))
+    assert np.array_equal(to_np(d2), od[pix])
+
+
+@pytest.mark.parametrize("res,storage", [(32, torch.float32), (160, torch.float32), (64, torch.float16)])
+def test_occupancy_bit_exact(res, storage):
+    print_case("occupancy res %d %s" % (res, storage))
+    p = Pair(res, seed=0, occupancy=True, storage=storage)
+    got = to_np(p.gpu.occupancy)
+    assert np.array_equal(got, p.orc.occ)
+    assert 0 < got.mean() < 1
+
+
+@pytest.mark.parametrize("n_samples", [1, 64, 100, 256])
+def test_render_rays_random(n_samples):
+    """Random rays (hits, misses, axis-aligned, inside-box starts), no
+    skipping or termination."""
+    import paper_2404_11852_amd as cic
+    print_case("render_rays random N=%d" % n_samples)
+    p = Pair(32, seed=3, mlp_seed=4, bias_std=0.2)
+    o, d = synth.random_rays(3000, seed=6)
+    go = cic.make_opts(n_samples, bg=(0.3, 0.6, 0.9))
+    rgb, dep, acc = cic.render_rays(p.gpu, go, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    orgb, odep, oacc = oracle.render_rays(p.orc, oracle.opts(n_samples, bg=(0.3, 0.6, 0.9)), o, d)
+    e1, _ = compare(to_np(rgb), orgb)
+    e2, _ = compare(to_np(dep), odep, what="depth_t")
+    e3, _ = compare(to_np(acc), oacc, what="acc")
+    print("max err rgb %.2e depth %.2e acc %.2e" % (e1, e2, e3))
+
+
+def test_render_frame_cfg1():
+    """64x64 frame, 32^3 grid, 64 samples, no skipping/termination."""
+    import paper_2404_11852_amd as cic
+    print_case("render_frame cfg1")
+    p = Pair(32, seed=0, mlp_seed=1)
+    gc, oc = cams(64, 64, synth.orbit_pose(0))
+    n_eval = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rgb, dz, acc = cic.render_frame(p.gpu, cic.make_opts(64), gc, n_eval=n_eval)
+    orgb, odz, oacc, diag = oracle.render_pixels(p.orc, oracle.opts(64), oc)
+    compare(to_np(rgb), orgb)
+    compare(to_np(acc), oacc, what="acc")
+    a = np.maximum(oacc, 1e-12)
+    fin = np.isfinite(odz)
+    assert np.array_equal(np.isfinite(to_np(dz)), fin)
+    derr = np.abs(to_np(dz)[fin] - odz[fin]) * a[fin] / (1 + np.abs(odz[fin]))
+    assert derr.max() < 2e-5, derr.max()
+    assert int(n_eval.item()) == int(diag["n_eval"].sum())
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_render_frame_skip_and_termination(order):
+    """160^3 scene with occupancy skipping and termination at 1e-4 on a
+    96x96 frame; voxel order must equal ray order bit for bit."""
+    import paper_2404_11852_amd as cic
+    print_case("render_frame skip+term order=%d" % order)
+    p = Pair(160, seed=0, mlp_seed=1, occupancy=True)
+    gc, oc = cams(96, 96, synth.orbit_pose(0))
+    n_eval = torch.zeros(1, dtype=torch.int64, device="cuda")
+    go = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=order)
+    rgb, dz, acc = cic.render_frame(p.gpu, go, gc, n_eval=n_eval)
+    orgb, odz, oacc, diag = oracle.render_pixels(p.orc, oracle.opts(256, 1e-4, True), oc)
+    e, nflag = compare(to_np(rgb), orgb, margin=diag["margin"])
+    compare(to_np(acc), oacc, margin=diag["margin"], what="acc")
+    print("max err %.2e, %d flip-band pixels" % (e, nflag))
+    ne = int(n_eval.item())
+    assert abs(ne - int(diag["n_eval"].sum())) <= 2 * nflag
+    if order == 1:
+        r2, d2, a2 = cic.render_frame(p.gpu, cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=0), gc)
+        assert torch.equal(rgb, r2) and torch.equal(acc, a2)
+        assert torch.equal(torch.nan_to_num(dz, posinf=-1), torch.nan_to_num(d2, posinf=-1))
+
+
+def test_render_frame_cfg2_sampled():
+    """Full 800x800, 160^3, 256 samples with skipping and termination, in the
+    launch configuration the benchmark times; 3000 seeded pixels checked
+    against the oracle one by one."""
+    import paper_2404_11852_amd as cic
+    print_case("render_frame cfg2 800x800 sampled")
+    p = Pair(160, seed=0, mlp_seed=1, occupancy=True)
+    gc, oc = cams(800, 800, synth.orbit_pose(0))
+    go = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=0)
+    rgb, dz, acc = cic.render_frame(p.gpu, go, gc)
+    pix = synth.pixel_subset(800, 800, 3000, seed=7)
+    orgb, odz, oacc, diag = oracle.render_pixels(p.orc, oracle.opts(256, 1e-4, True), oc, pix)
+    e, nflag = compare(to_np(rgb)[pix], orgb, margin=diag["margin"])
+    print("cfg2 sampled max err %.2e, %d flagged" % (e, nflag))
+    # void pixels agree away from the opacity cut
+    am = diag["acc_margin"]
+    assert np.array_equal(np.isinf(to_np(dz)[pix])[am > 1e-3], np.isinf(odz)[am > 1e-3])
+
+
+def test_render_fp16_grid_matches_oracle_on_same_values():
+    """FP16 grid storage: the oracle reads the same half-precision values
+    widened to float, so colours still agree to the float32 tolerance."""
+    import paper_2404_11852_amd as cic
+    print_case("render fp16 grid")
+    p = Pair(64, seed=2, mlp_seed=3, occupancy=True, storage=torch.float16)
+    gc, oc = cams(64, 64, synth.orbit_pose(20))
+    rgb, dz, acc = cic.render_frame(p.gpu, cic.make_opts(128, 1e-4, True), gc)
+    orgb, _, _, diag = oracle.render_pixels(p.orc, oracle.opts(128, 1e-4, True), oc)
+    compare(to_np(rgb), orgb, margin=diag["margin"])
+
+
+def test_edge_cases():
+    import paper_2404_11852_amd as cic
+    print_case("edge cases")
+    p = Pair(16, seed=1)
+    # rays that all miss the box
+    o = torch.tensor([[5.0, 5.0, 5.0], [0.0, 0.0, 4.0]], device="cuda")
+    d = torch.tensor([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]], device="cuda")
+    rgb, dep, acc = cic.render_rays(p.gpu, cic.make_opts(32, bg=(0.1, 0.2, 0.3)), o, d)
+    assert torch.equal(rgb, torch.tensor([[0.1, 0.2, 0.3]] * 2, device="cuda"))
+    assert torch.all(acc == 0) and torch.all(dep == 0)
+    # empty grid with skipping: background, opacity 0
+    dens = np.full((16, 16, 16), -30.0, np.float32)
+    q = Pair(16, dens=dens, feats=p.feats, mlp=p.mlp, occupancy=True)
+    assert int(q.gpu.occupancy.sum()) == 0
+    o, dd = synth.random_rays(200, seed=2)
+    rgb, dep, acc = cic.render_rays(q.gpu, cic.make_opts(64, 1e-4, True), torch.from_numpy(o).cuda(),
+                                    torch.from_numpy(dd).cuda())
+    assert torch.all(acc == 0) and torch.all(rgb == 1.0)
+    # n = 0
+    z = torch.empty((0, 3), device="cuda")
+    r0, _, _ = cic.render_rays(p.gpu, cic.make_opts(32), z, z)
+    assert r0.shape == (0, 3)
+    # maximum samples per ray
+    o, dd = synth.random_rays(64, seed=3)
+    rgb, dep, acc = cic.render_rays(p.gpu, cic.make_opts(1024), torch.from_numpy(o).cuda(), torch.from_numpy(dd).cuda())
+    orgb, odep, oacc = oracle.render_rays(p.orc, oracle.opts(1024), o, dd)
+    compare(to_np(rgb), orgb)
+
+
+def test_chunking_and_determinism():
+    """A batch larger than one pipeline pass (2^21 rays) equals the same rays
+    rendered in two calls; repeated calls are bit-identical."""
+    import paper_2404_11852_amd as cic
+    print_case("chunking 2.2M rays")
+    p = Pair(32, seed=5)
+    n = (1 << 21) + 12345
+    gc, _ = cams(1600, 1400, synth.orbit_pose(2))
+    o, d = cic.generate_rays(gc)
+    o, d = o[:n].contiguous(), d[:n].contiguous()
+    go = cic.make_opts(16)
+    a = cic.render_rays(p.gpu, go, o, d)
+    k = 1 << 20
+    b1 = cic.render_rays(p.gpu, go, o[:k].contiguous(), d[:k].contiguous())
+    b2 = cic.render_rays(p.gpu, go, o[k:].contiguous(), d[k:].contiguous())
+    for x, y1, y2 in zip(a, b1, b2):
+        assert torch.equal(x, torch.cat([y1, y2]))
+    a2 = cic.render_rays(p.gpu, go, o, d)
+    for x, y in zip(a, a2):
+        assert torch.equal(x, y)
