@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the dense-grid NeRF renderer with sparse radiance warping on
+one MI355X.
+
+Timed step: one full 800x800 frame of the 160^3 scene (FP32 grid and MLP, up
+to 256 samples per ray, occupancy skipping, early termination at 1e-4)
+through render_frame; value = evaluated ray samples per second (samples that
+pass through the MLP), inputs resident in HBM.  After the timed region the
+same JSON line reports the other measured forms as sub-objects: the 32-frame
+SpaRW orbit (FPS, mask fraction, PSNR against full renders), and the
+per-stage times.  The roofline object is for the dominant kernel (the
+feature-gather + MLP stage), timed with HIP events on its launch stream.
+The CPU baseline is the plain oracle on a bounded, seeded pixel sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray samples/s + 800x800 FPS (full vs SpaRW); fwd+bwd samples/s; BF16 vs FP32"
+MLP_FLOP_PER_SAMPLE = 2 * (12 * 128 + 128 * 128 + 128 * 3)   # 36,608 useful FLOP
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def psnr(a, b):
+    import torch
+    mse = torch.mean((a.double() - b.double()) ** 2).item()
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def build_scene(res, device):
+    import synth
+    import paper_2404_11852_amd as cic
+    dens, feats = synth.make_scene(res, seed=0)
+    mlp = synth.make_mlp(1)
+    model = cic.Model(dens, feats, mlp, device=device, density_shift=synth.DENSITY_SHIFT)
+    model.build_occupancy(synth.OCC_SIGMA)
+    return model, (dens, feats, mlp)
+
+
+def camera(W, H, pose):
+    import synth
+    import paper_2404_11852_amd as cic
+    f, cx, cy = synth.intrinsics(W, H)
+    return cic.make_camera(W, H, f, cx, cy, synth.as_f32(pose))
+
+
+def timed_frames(model, opts, cam, steps, warmup):
+    """Warm up, then time exactly `steps` render_frame calls."""
+    import torch
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    for _ in range(warmup):
+        cic.render_frame(model, opts, cam)
+    n_eval = torch.zeros(1, dtype=torch.int64, device=model.device)
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cic.render_frame(model, opts, cam, n_eval=n_eval)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = _lib.timing_read()
+    _lib.timing_enable(False)
+    return t1 - t0, int(n_eval.item()), stages
+
+
+def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16):
+    """32-frame orbit, references every 16th frame rendered in full, targets
+    warped from the nearest reference (ties to the earlier one) with holes
+    re-rendered.  Returns timing and quality against full renders."""
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    poses = [synth.orbit_pose(k) for k in range(n_frames)]
+    refs = list(range(0, n_frames, ref_every))
+    cams = [camera(W, H, p) for p in poses]
+
+    def nearest(k):
+        return min(refs, key=lambda r: (abs(k - r), r))
+
+    def run():
+        out = {}
+        ref_img = {}
+        nm = []
+        for k in range(n_frames):
+            if k in refs:
+                rgb, dz, _ = cic.render_frame(model, opts, cams[k])
+                ref_img[k] = (rgb, dz)
+                out[k] = rgb
+        for k in range(n_frames):
+            if k in refs:
+                continue
+            r = nearest(k)
+            T = synth.relative_pose(synth.as_f32(poses[r]), synth.as_f32(poses[k]))
+            rgb, dz, mask, n_masked = cic.render_frame_sparw(model, opts, cams[r], ref_img[r][0], ref_img[r][1],
+                                                             cams[k], torch.from_numpy(T))
+            out[k] = rgb
+            nm.append(n_masked)
+        return out, nm
+
+    run()   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, nm = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # per-target time, references excluded
+    ref_rgbd = {r: cic.render_frame(model, opts, cams[r])[:2] for r in refs}
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    for k in range(n_frames):
+        if k in refs:
+            continue
+        r = nearest(k)
+        T = synth.relative_pose(synth.as_f32(poses[r]), synth.as_f32(poses[k]))
+        cic.render_frame_sparw(model, opts, cams[r], ref_rgbd[r][0], ref_rgbd[r][1], cams[k], torch.from_numpy(T))
+    torch.cuda.synchronize()
+    tt1 = time.perf_counter()
+    full_t0 = time.perf_counter()
+    full = [cic.render_frame(model, opts, c)[0] for c in cams]
+    torch.cuda.synchronize()
+    full_t1 = time.perf_counter()
+    ps = [psnr(out[k], full[k]) for k in range(n_frames) if k not in refs]
+    fr = [int(x.item()) / float(W * H) for x in nm]
+    n_t = n_frames - len(refs)
+    return {
+        "frames": n_frames, "references": len(refs), "window": ref_every,
+        "fps": n_frames / (t1 - t0),
+        "fps_full_render": n_frames / (full_t1 - full_t0),
+        "speedup_vs_full": (full_t1 - full_t0) / (t1 - t0),
+        "ms_per_target": 1e3 * (tt1 - tt0) / n_t,
+        "mask_fraction_mean": sum(fr) / len(fr), "mask_fraction_max": max(fr),
+        "psnr_vs_full_mean_db": sum(ps) / len(ps), "psnr_vs_full_min_db": min(ps),
+    }
+
+
+def cpu_baseline(scene, target_s=12.0):
+    """The oracle, as it stands, on a seeded pixel sample of the same frame."""
+    import numpy as np
+    import oracle
+    import synth
+    dens, feats, mlp = scene
+    om = oracle.Model(dens, feats, mlp, density_shift=synth.DENSITY_SHIFT)
+    om.set_occupancy(oracle.build_occupancy(om, synth.OCC_SIGMA))
+    f, cx, cy = synth.intrinsics(800, 800)
+    oc = oracle.camera(800, 800, f, cx, cy, synth.as_f32(synth.orbit_pose(0)))
+    op = oracle.opts(256, 1e-4, True)
+    n = 512
+    while True:
+        pix = synth.pixel_subset(800, 800, n, seed=99)
+        t0 = time.perf_counter()
+        _, _, _, diag = oracle.render_pixels(om, op, oc, pix)
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 4 or n >= 640000:
+            break
+        n = min(640000, int(n * max(2.0, (target_s / 4) / max(dt, 1e-3))))
+    if dt < target_s and n < 640000:
+        n = min(640000, int(n * target_s / max(dt, 1e-3)))
+        pix = synth.pixel_subset(800, 800, n, seed=99)
+        t0 = time.perf_counter()
+        _, _, _, diag = oracle.render_pixels(om, op, oc, pix)
+        dt = time.perf_counter() - t0
+    ns = int(diag["n_eval"].sum())
+    return {"value": ns / dt, "unit": "samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d seeded pixels of the 800x800 frame (%d evaluated samples, %.1f s)" % (n, ns, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--order", choices=["ray", "voxel"], default="ray")
+    ap.add_argument("--skip-sparw", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rays would shard by pixel tiles with the grid replicated; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2404_11852_amd as cic
+    device = "cuda:0"
+    W = H = 800
+    log("building 160^3 scene")
+    model, scene = build_scene(160, device)
+    opts = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True,
+                         order=cic.CIC_ORDER_VOXEL if args.order == "voxel" else cic.CIC_ORDER_RAY)
+    cam = camera(W, H, __import__("synth").orbit_pose(0))
+
+    log("timing %d frames after %d warm-up" % (args.steps, args.warmup))
+    dt, n_eval, stages = timed_frames(model, opts, cam, args.steps, args.warmup)
+    ms_step = 1e3 * dt / args.steps
+    samples_per_frame = n_eval / args.steps
+    value = n_eval / dt
+    mlp_ms, mlp_n = stages["mlp"]
+    mlp_ms_per = mlp_ms / max(mlp_n, 1)
+    achieved = MLP_FLOP_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e12
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
+    log("%.3f ms/frame, %.3g samples/s, mlp %.3f ms/launch" % (ms_step, value, mlp_ms_per))
+
+    # the other order, for the memory-centric A/B
+    other = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True,
+                          order=cic.CIC_ORDER_RAY if args.order == "voxel" else cic.CIC_ORDER_VOXEL)
+    dt2, n2, st2 = timed_frames(model, other, cam, max(5, args.steps // 2), 1)
+    ab = {"order": "voxel" if args.order == "ray" else "ray", "ms_per_frame": 1e3 * dt2 / max(5, args.steps // 2),
+          "stage_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st2.items() if v[1]}}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "800x800 full-frame render, 160^3 dense grid (raw density + 12 features, FP32), "
+                               "up to 256 samples/ray, occupancy skip, termination at T<1e-4, "
+                               "39-128-128-3 MLP (FP32 MFMA)",
+                   "width": W, "height": H, "grid_res": 160, "n_samples": 256, "order": args.order},
+        "fps_full_800x800": 1e3 / ms_step,
+        "evaluated_samples_per_frame": samples_per_frame,
+        "stage_ms_per_launch": stage_ms,
+        "order_ab": ab,
+        "roofline": {"bound": "mfma", "kernel": "k_mlp_fwd_f32 (feature gather + MLP)",
+                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flop_per_launch": MLP_FLOP_PER_SAMPLE * samples_per_frame,
+                     "ms_per_launch": mlp_ms_per},
+    }
+    if not args.skip_sparw:
+        log("SpaRW orbit")
+        out["sparw"] = sparw_orbit(model, opts, W, H)
+    if not args.skip_cpu:
+        log("CPU baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(scene)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

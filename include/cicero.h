@@ -74,7 +74,7 @@ enum {
 };
 
 typedef struct {
-    int32_t res[3];            /* vertices per axis, each in [2, 2048] */
+    int32_t res[3];            /* vertices per axis, each in [2, 1024] */
     int32_t n_feat;            /* feature channels; must be 12 */
     int32_t storage;           /* CIC_F32 or CIC_F16 (density and features) */
     float box_lo[3];
@@ -122,8 +122,9 @@ const char *cic_last_error_message(void);
  * voxel of each sample, Sec. II-B; skipping empty voxels is the usual
  * companion of dense-grid models).  occ[v] = 1 iff any of the voxel's eight
  * vertices has softplus(raw + density_shift) > occ_sigma, evaluated as
- * (raw + density_shift) > logf(expm1(occ_sigma)) in float32.  float32 grids
- * only.  occ: device, (res0-1)(res1-1)(res2-1) bytes. */
+ * (raw + density_shift) > log(expm1(occ_sigma)) in float32 (the threshold
+ * is computed in float64 on the host and rounded once).  float16 grids are
+ * widened to float32 first.  occ: device, (res0-1)(res1-1)(res2-1) bytes. */
 int build_occupancy(const cic_grid *grid, float occ_sigma, uint8_t *occ, cic_stream_t stream);
 
 /* One ray per pixel (Sec. II-B Indexing): origin = camera centre,
@@ -206,6 +207,25 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
                     float *d_density, float *d_features,
                     float *d_w0, float *d_b0, float *d_w1, float *d_b1, float *d_w2, float *d_b2,
                     void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* Stage timing for benchmarks.  While enabled (per calling thread), every
+ * kernel launch of the stages below is bracketed by HIP events recorded on
+ * the launch stream.  cic_timing_read waits for the recorded events and
+ * writes, per stage, the summed milliseconds and the number of launches
+ * since the last enable; it fills at most n_stages entries of each array
+ * (host pointers).  Stages: */
+enum {
+    CIC_STAGE_MARCH = 0,      /* ray march + transmittance scan */
+    CIC_STAGE_COMPACT = 1,    /* count scan, compaction, voxel bucketing */
+    CIC_STAGE_MLP = 2,        /* feature gather + MLP (forward) */
+    CIC_STAGE_REDUCE = 3,     /* per-ray accumulation */
+    CIC_STAGE_WARP = 4,       /* z-buffer splat + resolve */
+    CIC_STAGE_RAYGEN = 5,     /* pixel rays */
+    CIC_STAGE_BACKWARD = 6,   /* adjoint kernels */
+    CIC_STAGE_COUNT = 7
+};
+int cic_timing_enable(int on);
+int cic_timing_read(double *ms, int64_t *launches, int n_stages);
 
 #ifdef __cplusplus
 }

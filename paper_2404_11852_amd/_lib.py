@@ -49,7 +49,9 @@ class Camera(C.Structure):
 
 
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
-           "render_frame", "warp_frame", "render_frame_sparw", "render_backward"]
+           "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
+           "cic_timing_read"]
+STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "backward"]
 
 _lib = None
 _lock = threading.Lock()
@@ -77,6 +79,8 @@ def lib():
                 L.render_frame_sparw.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
                 L.render_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                               vp, vp, u64, vp]
+                L.cic_timing_enable.argtypes = [C.c_int]
+                L.cic_timing_read.argtypes = [vp, vp, C.c_int]
                 for name in EXPORTS[2:]:
                     getattr(L, name).restype = C.c_int
                 _lib = L
@@ -225,3 +229,16 @@ def render_backward(grid, mlp, opts, rays_o, rays_d, d_rgb, d_depth_t, d_acc, gr
                                  _ptr(grads["density"]), _ptr(grads["features"]), _ptr(grads["w0"]),
                                  _ptr(grads["b0"]), _ptr(grads["w1"]), _ptr(grads["b1"]), _ptr(grads["w2"]),
                                  _ptr(grads["b2"]), _ptr(ws), C.c_size_t(ws.numel()), _stream()))
+
+
+def timing_enable(on=True):
+    _check(lib().cic_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """{stage: (milliseconds, launches)} since the last timing_enable."""
+    n = len(STAGES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    _check(lib().cic_timing_read(ms, cnt, n))
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}

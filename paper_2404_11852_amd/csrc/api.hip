@@ -7,6 +7,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 
@@ -265,24 +266,88 @@ int check_ws(size_t need, void *ws, size_t ws_bytes)
 
 void *align_ws(void *ws) { return (void *)(((uintptr_t)ws + 255) & ~(uintptr_t)255); }
 
+// Stage timing (benchmarks): events recorded around launches while enabled.
+struct TimedLaunch {
+    int stage;
+    hipEvent_t a, b;
+};
+struct Timing {
+    bool on = false;
+    std::vector<TimedLaunch> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+};
+thread_local Timing g_timing;
+
+// Brackets the launches issued during its lifetime.
+struct StageTimer {
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageTimer(int st, hipStream_t str) : stage(st), s(str)
+    {
+        if (g_timing.on) {
+            a = g_timing.get();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~StageTimer()
+    {
+        if (a) {
+            hipEvent_t b = g_timing.get();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                g_timing.recs.push_back(TimedLaunch{stage, a, b});
+            } else {
+                g_timing.pool.push_back(a);
+            }
+        }
+    }
+};
+
 // Full render pipeline on one pass of rays.
 void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, const OptsK &ok_, bool voxel,
                   RenderBufs &b, float *rgb, float *depth, float *acc, const int32_t *out_map,
                   const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s)
 {
     const bool f16 = grid->storage == CIC_F16;
-    if (f16) launch_march<__half>(gk, ok_, b, s);
-    else launch_march<float>(gk, ok_, b, s);
-    launch_exclusive_scan(b.count, b.offsets, b.scan_tmp, b.n, s);
-    if (voxel) launch_fill_u32(b.brick_off, 0u, b.n_bricks + 1, s);
-    launch_compact(gk, b, voxel, s);
-    if (voxel) {
-        launch_exclusive_scan(b.brick_off, b.brick_off, b.brick_tmp, b.n_bricks, s);
-        launch_brick_scatter(b, s);
+    {
+        StageTimer t(CIC_STAGE_MARCH, s);
+        if (f16) launch_march<__half>(gk, ok_, b, s);
+        else launch_march<float>(gk, ok_, b, s);
     }
-    if (f16) launch_mlp_forward<__half>(gk, *mlp, b, voxel, s);
-    else launch_mlp_forward<float>(gk, *mlp, b, voxel, s);
-    launch_reduce(b, ok_, rgb, depth, acc, out_map, frame_cam, n_eval, s);
+    {
+        StageTimer t(CIC_STAGE_COMPACT, s);
+        launch_exclusive_scan(b.count, b.offsets, b.scan_tmp, b.n, s);
+        if (voxel) launch_fill_u32(b.brick_off, 0u, b.n_bricks + 1, s);
+        launch_compact(gk, b, voxel, s);
+        if (voxel) {
+            launch_exclusive_scan(b.brick_off, b.brick_off, b.brick_tmp, b.n_bricks, s);
+            launch_brick_scatter(b, s);
+        }
+    }
+    {
+        StageTimer t(CIC_STAGE_MLP, s);
+        if (f16) launch_mlp_forward<__half>(gk, *mlp, b, voxel, s);
+        else launch_mlp_forward<float>(gk, *mlp, b, voxel, s);
+    }
+    {
+        StageTimer t(CIC_STAGE_REDUCE, s);
+        launch_reduce(b, ok_, rgb, depth, acc, out_map, frame_cam, n_eval, s);
+    }
 }
 
 }  // namespace
@@ -382,7 +447,10 @@ int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
         const int64_t nc = (np - c0) < kChunkRays ? (np - c0) : kChunkRays;
         Carver cv(align_ws(ws));
         RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, true);
-        launch_generate_rays(*cam, nc, c0, nullptr, nullptr, nullptr, (float *)b.rays_o, (float *)b.rays_d, s);
+        {
+            StageTimer t(CIC_STAGE_RAYGEN, s);
+            launch_generate_rays(*cam, nc, c0, nullptr, nullptr, nullptr, (float *)b.rays_o, (float *)b.rays_d, s);
+        }
         run_pipeline(grid, gk, mlp, ok_, voxel, b, rgb + 3 * c0, depth_z + c0, acc ? acc + c0 : nullptr, nullptr,
                      cam, n_eval, s);
     }
@@ -409,8 +477,11 @@ int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_t
     if ((rc = check_device())) return rc;
     Carver cv(align_ws(ws));
     WarpBufs w = carve_warp(cv, np, false);
-    launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, tgt_rgb, tgt_depth_z, mask, src_index, nullptr,
-                nullptr, (hipStream_t)stream);
+    {
+        StageTimer t(CIC_STAGE_WARP, (hipStream_t)stream);
+        launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, tgt_rgb, tgt_depth_z, mask, src_index,
+                    nullptr, nullptr, (hipStream_t)stream);
+    }
     return after_launch("warp_frame");
 }
 
@@ -442,9 +513,15 @@ int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts 
     WarpBufs w = carve_warp(cv, np, true);
     RenderBufs b = carve_render(cv, np, opts->n_samples, n_bricks_of(grid), voxel, true);
     b.n_active = w.n_holes;
-    launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, out_rgb, out_depth_z, mask, nullptr,
-                w.hole_idx, w.n_holes, s);
-    launch_generate_rays(*tgt, np, 0, nullptr, w.hole_idx, w.n_holes, (float *)b.rays_o, (float *)b.rays_d, s);
+    {
+        StageTimer t(CIC_STAGE_WARP, s);
+        launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, out_rgb, out_depth_z, mask, nullptr,
+                    w.hole_idx, w.n_holes, s);
+    }
+    {
+        StageTimer t(CIC_STAGE_RAYGEN, s);
+        launch_generate_rays(*tgt, np, 0, nullptr, w.hole_idx, w.n_holes, (float *)b.rays_o, (float *)b.rays_d, s);
+    }
     run_pipeline(grid, gk, mlp, ok_, voxel, b, out_rgb, out_depth_z, nullptr, w.hole_idx, tgt, n_eval, s);
     if (n_masked) launch_sparw_finish(w.n_holes, n_masked, s);
     return after_launch("render_frame_sparw");
@@ -459,6 +536,36 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     (void)d_acc; (void)d_density; (void)d_features; (void)d_w0; (void)d_b0; (void)d_w1; (void)d_b1; (void)d_w2;
     (void)d_b2; (void)ws; (void)ws_bytes; (void)stream;
     return fail(CIC_ERR_INVALID, "render_backward is not available in this build");
+}
+
+int cic_timing_enable(int on)
+{
+    for (auto &r : g_timing.recs) {
+        g_timing.pool.push_back(r.a);
+        g_timing.pool.push_back(r.b);
+    }
+    g_timing.recs.clear();
+    g_timing.on = on != 0;
+    return ok();
+}
+
+int cic_timing_read(double *ms, int64_t *launches, int n_stages)
+{
+    if (n_stages < 0 || (n_stages > 0 && (!ms || !launches))) return fail(CIC_ERR_INVALID, "bad timing arrays");
+    for (int i = 0; i < n_stages; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto &r : g_timing.recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(CIC_ERR_HIP, "hipEventSynchronize failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(CIC_ERR_HIP, "hipEventElapsedTime failed");
+        if (r.stage >= 0 && r.stage < n_stages) {
+            ms[r.stage] += t;
+            launches[r.stage] += 1;
+        }
+    }
+    return ok();
 }
 
 }  // extern "C"
