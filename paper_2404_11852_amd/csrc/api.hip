@@ -195,6 +195,17 @@ WarpBufs carve_warp(Carver &cv, int64_t np, bool holes)
 
 constexpr int64_t kChunkRaysBwd = 4096;
 
+// Extra buffers of a backward pass (after carve_render's).
+void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &bb)
+{
+    const int64_t ns = nc * (int64_t)N;
+    b.slot_t = cv.take<float>(ns);
+    b.rec_t = cv.take<float>(ns);
+    b.stage = cv.take<float>(ns * kStageStride);
+    bb.rec_dc = cv.take<float>(3 * ns);
+    bb.partials = cv.take<float>((int64_t)kWgBlocks * kPartialFloats);
+}
+
 size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
 {
     Carver cv(nullptr);
@@ -217,7 +228,9 @@ size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
         break;
     case CIC_OP_RENDER_BACKWARD: {
         const int64_t nc = n < kChunkRaysBwd ? n : kChunkRaysBwd;
-        carve_render(cv, nc, o->n_samples, nb, voxel, false);
+        RenderBufs b = carve_render(cv, nc, o->n_samples, nb, false, false);
+        BackwardBufs bb{};
+        carve_backward(cv, nc, o->n_samples, b, bb);
         break;
     }
     default:
@@ -532,10 +545,61 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
                     const float *d_acc, float *d_density, float *d_features, float *d_w0, float *d_b0, float *d_w1,
                     float *d_b1, float *d_w2, float *d_b2, void *ws, size_t ws_bytes, cic_stream_t stream)
 {
-    (void)grid; (void)mlp; (void)opts; (void)n_rays; (void)rays_o; (void)rays_d; (void)d_rgb; (void)d_depth_t;
-    (void)d_acc; (void)d_density; (void)d_features; (void)d_w0; (void)d_b0; (void)d_w1; (void)d_b1; (void)d_w2;
-    (void)d_b2; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(CIC_ERR_INVALID, "render_backward is not available in this build");
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
+    if (grid->storage != CIC_F32) return fail(CIC_ERR_INVALID, "render_backward needs a float32 grid");
+    if (n_rays < 0) return fail(CIC_ERR_INVALID, "n_rays < 0");
+    if (n_rays == 0) return ok();
+    if (!rays_o || !rays_d || !d_rgb) return fail(CIC_ERR_INVALID, "rays or d_rgb is NULL");
+    if (!d_density || !d_features || !d_w0 || !d_b0 || !d_w1 || !d_b1 || !d_w2 || !d_b2)
+        return fail(CIC_ERR_INVALID, "gradient pointer is NULL");
+    const size_t need = bytes_for(CIC_OP_RENDER_BACKWARD, n_rays, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    const int64_t nb = n_bricks_of(grid);
+    for (int64_t c0 = 0; c0 < n_rays; c0 += kChunkRaysBwd) {
+        const int64_t nc = (n_rays - c0) < kChunkRaysBwd ? (n_rays - c0) : kChunkRaysBwd;
+        Carver cv(align_ws(ws));
+        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, false, false);
+        BackwardBufs bb{};
+        carve_backward(cv, nc, opts->n_samples, b, bb);
+        b.rays_o = rays_o + 3 * c0;
+        b.rays_d = rays_d + 3 * c0;
+        bb.d_rgb = d_rgb + 3 * c0;
+        bb.d_depth_t = d_depth_t ? d_depth_t + c0 : nullptr;
+        bb.d_acc = d_acc ? d_acc + c0 : nullptr;
+        bb.d_density = d_density;
+        bb.d_features = d_features;
+        bb.d_w0 = d_w0;
+        bb.d_b0 = d_b0;
+        bb.d_w1 = d_w1;
+        bb.d_b1 = d_b1;
+        bb.d_w2 = d_w2;
+        bb.d_b2 = d_b2;
+        {
+            StageTimer t(CIC_STAGE_MARCH, s);
+            launch_march<float>(gk, ok_, b, s);
+        }
+        {
+            StageTimer t(CIC_STAGE_COMPACT, s);
+            launch_exclusive_scan(b.count, b.offsets, b.scan_tmp, b.n, s);
+            launch_compact(gk, b, false, s);
+        }
+        {
+            StageTimer t(CIC_STAGE_MLP, s);
+            launch_mlp_forward_staged(gk, *mlp, b, s);
+        }
+        {
+            StageTimer t(CIC_STAGE_BACKWARD, s);
+            launch_backward_composite(gk, ok_, b, bb, s);
+            launch_mlp_backward(gk, *mlp, b, bb, s);
+            launch_weight_grads(b, bb, s);
+        }
+    }
+    return after_launch("render_backward");
 }
 
 int cic_timing_enable(int on)

@@ -1,0 +1,404 @@
+// Adjoint of the rendering quadrature, the MLP and the trilinear gathers.
+//
+// With C = sum_k w_k c_k + T_stop bg, w_k = T_k (1 - e^{-sigma_k delta}) and
+// T_{k+1} = T_k e^{-sigma_k delta}, the derivative with respect to the
+// density of live sample k is
+//   dC/dsigma_k = delta (T_{k+1} c_k - R_k),  R_k = sum_{j>k} w_j c_j + T_stop bg,
+// (every later weight and the background term scale with T_{k+1}), the
+// expected distance gives delta (T_{k+1} t_k - D_k) with D_k = sum_{j>k} w_j t_j,
+// and the opacity 1 - T_stop gives delta T_stop.  dC/dc_k = w_k.
+//
+// Kernels (one backward pass over a chunk of rays; the forward has already
+// been recomputed into the workspace, with per-sample MLP vectors staged):
+//  - k_bwd_composite: one wavefront per ray walks its live samples from the
+//    back, 64 at a time, with a reverse wavefront scan for R_k and D_k; it
+//    writes dL/dc_k and scatter-adds dL/draw through the trilinear weights.
+//  - k_mlp_bwd: per 32-sample batch, the output-layer adjoint on the vector
+//    ALUs, then W1^T and W0^T products on FP32 MFMA (transposed weight
+//    fragments in LDS); hidden-layer gradients are staged for the weight
+//    gradients and the feature gradient is scatter-added to the grid.
+//  - k_wgrad: weight gradients as split-K MFMA products over the staged
+//    per-sample vectors, one partial per block, reduced in a fixed order by
+//    k_wgrad_apply (deterministic).
+#include "kernels.h"
+
+namespace cic {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// Reverse inclusive scan (sum over lanes >= this lane).
+__device__ __forceinline__ float wave_rev_incl_scan(float v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const float u = __shfl_down(v, off, kWave);
+        if (l + off < kWave) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void scatter_trilinear(float *grad, const GridK &g, const int i0[3], const float fr[3],
+                                                  int stride, int ch, float v)
+{
+    const float wx[2] = {1.f - fr[0], fr[0]}, wy[2] = {1.f - fr[1], fr[1]}, wz[2] = {1.f - fr[2], fr[2]};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+        const float w = wx[dx] * wy[dy] * wz[dz];
+        atomicAdd(grad + vertex_index(g, i0[0] + dx, i0[1] + dy, i0[2] + dz) * stride + ch, w * v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_composite(GridK g, OptsK op, RenderBufs b, BackwardBufs bb)
+{
+    const int lane = lane_id();
+    const int64_t ray = (int64_t)blockIdx.x * 4 + (threadIdx.x / kWave);
+    if (ray >= b.n) return;
+    const uint32_t cnt = b.count[ray];
+    if (cnt == 0) return;
+    const uint32_t off = b.offsets[ray];
+    const RayInfo inf = b.info[ray];
+    const float gr[3] = {bb.d_rgb[3 * ray], bb.d_rgb[3 * ray + 1], bb.d_rgb[3 * ray + 2]};
+    const float gd = bb.d_depth_t ? bb.d_depth_t[ray] : 0.f;
+    const float ga = bb.d_acc ? bb.d_acc[ray] : 0.f;
+    float o[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[a] = b.rays_o[3 * ray + a];
+        d[a] = b.rays_d[3 * ray + a];
+    }
+    const float *dens = (const float *)g.density;
+    float carry[3] = {inf.t_stop * op.bg[0], inf.t_stop * op.bg[1], inf.t_stop * op.bg[2]};
+    float carry_d = 0.f;
+    const int nch = (int)((cnt + kWave - 1) / kWave);
+    for (int chn = nch - 1; chn >= 0; --chn) {
+        const uint32_t j = (uint32_t)chn * kWave + lane;
+        const bool act = j < cnt;
+        float w = 0.f, T = 0.f, c[3] = {0.f, 0.f, 0.f}, tk = 0.f;
+        int i0[3] = {0, 0, 0};
+        float fr[3] = {0.f, 0.f, 0.f};
+        if (act) {
+            const int64_t r = (int64_t)off + j;
+            w = b.rec_w[r];
+            T = b.rec_t[r];
+            c[0] = b.rec_c[3 * r];
+            c[1] = b.rec_c[3 * r + 1];
+            c[2] = b.rec_c[3 * r + 2];
+            sample_voxel(o, d, inf.tn, inf.delta, b.rec_k[r], g, i0, fr, tk);
+        }
+        float R[3], incl[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            incl[ch] = wave_rev_incl_scan(w * c[ch]);
+            R[ch] = carry[ch] + (incl[ch] - w * c[ch]);
+        }
+        const float incl_d = wave_rev_incl_scan(w * tk);
+        const float D = carry_d + (incl_d - w * tk);
+        if (act) {
+            const int64_t r = (int64_t)off + j;
+            const float Tn = T - w;   // T_{k+1} = T_k (1 - alpha_k)
+            float ds = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) ds = fmaf(gr[ch], fmaf(Tn, c[ch], -R[ch]), ds);
+            ds = fmaf(gd, fmaf(Tn, tk, -D), ds);
+            ds = fmaf(ga, inf.t_stop, ds);
+            ds *= inf.delta;
+            const float raw = trilerp1(dens, g, i0, fr, 1, 0);
+            const float draw = ds * sigmoidf(raw + g.shift);
+            scatter_trilinear(bb.d_density, g, i0, fr, 1, 0, draw);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) bb.rec_dc[3 * r + ch] = w * gr[ch];
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) carry[ch] += __shfl(incl[ch], 0, kWave);
+        carry_d += __shfl(incl_d, 0, kWave);
+    }
+}
+
+void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
+                               hipStream_t s)
+{
+    if (b.n == 0) return;
+    hipLaunchKernelGGL(k_bwd_composite, dim3((unsigned)((b.n + 3) / 4)), dim3(256), 0, s, g, o, b, bb);
+}
+
+// ---------------------------------------------------------------------------
+// MLP backward
+// ---------------------------------------------------------------------------
+constexpr int kBwdWaves = 8;
+constexpr int kBNT = 2;
+// LDS (floats): W1T fragments [ti 8][c4 8][lane 64][4], W0T fragments
+// [c4 8][lane 64][4], W2 [q 4][ch 3][t 8][r 4]
+constexpr int kBOffW1T = 0;
+constexpr int kBOffW0T = kBOffW1T + 8 * 8 * 64 * 4;
+constexpr int kBOffW2 = kBOffW0T + 8 * 64 * 4;
+constexpr int kBLds = kBOffW2 + 384;
+
+__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
+{
+    extern __shared__ float lds[];
+    const int nthr = blockDim.x;
+    for (int i = threadIdx.x; i < 8 * 8 * 64 * 4; i += nthr) {
+        const int rr = i & 3, l = (i >> 2) & 63, c4 = (i >> 8) & 7, ti = i >> 11;
+        lds[kBOffW1T + i] = m.w1[(16 * c4 + 4 * (l >> 4) + rr) * 128 + 16 * ti + (l & 15)];
+    }
+    for (int i = threadIdx.x; i < 8 * 64 * 4; i += nthr) {
+        const int rr = i & 3, l = (i >> 2) & 63, c4 = i >> 8;
+        const int col = l & 15;
+        lds[kBOffW0T + i] = col < 12 ? m.w0[(16 * c4 + 4 * (l >> 4) + rr) * 39 + col] : 0.f;
+    }
+    for (int i = threadIdx.x; i < 384; i += nthr) {
+        const int q = i / 96, ch = (i / 32) % 3, t = (i / 4) % 8, r = i & 3;
+        lds[kBOffW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
+    }
+    __syncthreads();
+
+    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+    const int wave = threadIdx.x / 64;
+    const int64_t total = (int64_t)b.offsets[b.n];
+    const int64_t nbatch = (total + 16 * kBNT - 1) / (16 * kBNT);
+    const f4_t *w1t = (const f4_t *)(lds + kBOffW1T);
+    const f4_t *w0t = (const f4_t *)(lds + kBOffW0T);
+    const f4_t *w2l = (const f4_t *)(lds + kBOffW2);
+    float *dfeat_grad = bb.d_features;
+
+    for (int64_t bt = (int64_t)blockIdx.x * kBwdWaves + wave; bt < nbatch; bt += (int64_t)gridDim.x * kBwdWaves) {
+        int64_t rec[kBNT];
+        bool valid[kBNT];
+        f4_t dp1[8][kBNT];
+        f4_t h1m[8][kBNT];   // h1 > 0 masks as values
+#pragma unroll
+        for (int nt = 0; nt < kBNT; ++nt) {
+            const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
+            valid[nt] = s < total;
+            rec[nt] = valid[nt] ? s : 0;
+            const float *row = b.stage + rec[nt] * kStageStride;
+            float dl[3] = {0.f, 0.f, 0.f};
+            if (valid[nt]) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float c = b.rec_c[3 * rec[nt] + ch];
+                    dl[ch] = bb.rec_dc[3 * rec[nt] + ch] * c * (1.f - c);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const f4_t h2 = valid[nt] ? *(const f4_t *)(row + kStH2 + 16 * t + 4 * q) : f4_t{0.f, 0.f, 0.f, 0.f};
+                h1m[t][nt] = valid[nt] ? *(const f4_t *)(row + kStH1 + 16 * t + 4 * q) : f4_t{0.f, 0.f, 0.f, 0.f};
+                const f4_t wa = w2l[(q * 3 + 0) * 8 + t], wb = w2l[(q * 3 + 1) * 8 + t], wc = w2l[(q * 3 + 2) * 8 + t];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = fmaf(wa[r], dl[0], fmaf(wb[r], dl[1], wc[r] * dl[2]));
+                    dp1[t][nt][r] = h2[r] > 0.f ? v : 0.f;
+                }
+            }
+            if (valid[nt]) {
+                float *wrow = b.stage + rec[nt] * kStageStride;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) *(f4_t *)(wrow + kStDP1 + 16 * t + 4 * q) = dp1[t][nt];
+                *(f4_t *)(wrow + kStDL + 4 * q) = (q == 0) ? f4_t{dl[0], dl[1], dl[2], 0.f} : f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        // dh1 = W1^T dp1, dp0 = dh1 * [h1 > 0]
+        f4_t dp0[8][kBNT];
+#pragma unroll
+        for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+            for (int nt = 0; nt < kBNT; ++nt) dp0[ti][nt] = f4_t{0.f, 0.f, 0.f, 0.f};
+        {
+            f4_t a = w1t[lane];
+#pragma unroll
+            for (int ti = 0; ti < 8; ++ti) {
+#pragma unroll
+                for (int c4 = 0; c4 < 8; ++c4) {
+                    const int nx = (ti * 8 + c4 + 1 < 64) ? (ti * 8 + c4 + 1) : (ti * 8 + c4);
+                    const f4_t an = w1t[nx * 64 + lane];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                        for (int nt = 0; nt < kBNT; ++nt)
+                            dp0[ti][nt] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp1[c4][nt][rr], dp0[ti][nt], 0, 0, 0);
+                    a = an;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+            for (int nt = 0; nt < kBNT; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dp0[ti][nt][r] = h1m[ti][nt][r] > 0.f ? dp0[ti][nt][r] : 0.f;
+#pragma unroll
+        for (int nt = 0; nt < kBNT; ++nt)
+            if (valid[nt]) {
+                float *wrow = b.stage + rec[nt] * kStageStride;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) *(f4_t *)(wrow + kStDP0 + 16 * t + 4 * q) = dp0[t][nt];
+            }
+        // feature gradient = (W0^T dp0)[0:12], scattered to the grid
+        f4_t df[kBNT];
+#pragma unroll
+        for (int nt = 0; nt < kBNT; ++nt) df[nt] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c4 = 0; c4 < 8; ++c4) {
+            const f4_t a = w0t[c4 * 64 + lane];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int nt = 0; nt < kBNT; ++nt)
+                    df[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp0[c4][nt][rr], df[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < kBNT; ++nt) {
+            if (!valid[nt] || q >= 3) continue;
+            const uint32_t ray = b.rec_ray[rec[nt]];
+            const RayInfo inf = b.info[ray];
+            float o[3], d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                o[a] = b.rays_o[3 * (int64_t)ray + a];
+                d[a] = b.rays_d[3 * (int64_t)ray + a];
+            }
+            int i0[3];
+            float fr[3], tk;
+            sample_voxel(o, d, inf.tn, inf.delta, b.rec_k[rec[nt]], g, i0, fr, tk);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) scatter_trilinear(dfeat_grad, g, i0, fr, 12, 4 * q + r, df[nt][r]);
+        }
+    }
+}
+
+static int num_cus_b()
+{
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 256;
+}
+
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb,
+                         hipStream_t s)
+{
+    const int lds = kBLds * (int)sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb);
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: out[o][i] = sum_s A[s][a_col + o] * B[s][b_col + i] over
+// the staged rows, split over kWgBlocks blocks (each a contiguous range of
+// samples), one partial matrix per block
+// ---------------------------------------------------------------------------
+constexpr int kWgStep = 32;   // samples staged in LDS per step
+
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_wgrad(const float *stage, const uint32_t *total_p, int a_col, int b_col,
+                                               float *partials, int64_t slab)
+{
+    constexpr int MT = M / 16, NTL = N / 16, TILES = MT * NTL;
+    constexpr int TPW = (TILES + 3) / 4;
+    __shared__ float As[kWgStep][M + 4];
+    __shared__ float Bs[kWgStep][N + 4];
+    const int lane = lane_id(), wave = threadIdx.x / 64;
+    const int64_t total = (int64_t)*total_p;
+    const int64_t s0 = (int64_t)blockIdx.x * slab;
+    const int64_t s1 = (s0 + slab < total) ? s0 + slab : total;
+    f4_t acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int64_t sb = s0; sb < s1; sb += kWgStep) {
+        for (int e = threadIdx.x; e < kWgStep * M; e += 256) {
+            const int r = e / M, c = e % M;
+            As[r][c] = (sb + r < s1) ? stage[(sb + r) * kStageStride + a_col + c] : 0.f;
+        }
+        for (int e = threadIdx.x; e < kWgStep * N; e += 256) {
+            const int r = e / N, c = e % N;
+            Bs[r][c] = (sb + r < s1) ? stage[(sb + r) * kStageStride + b_col + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kWgStep; kk += 4) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+                const int tile = wave * TPW + i;
+                if (tile < TILES) {
+                    const int mt = tile / NTL, ntl = tile % NTL;
+                    const float a = As[kk + (lane >> 4)][16 * mt + (lane & 15)];
+                    const float bv = Bs[kk + (lane >> 4)][16 * ntl + (lane & 15)];
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *out = partials + (int64_t)blockIdx.x * M * N;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int tile = wave * TPW + i;
+        if (tile < TILES) {
+            const int mt = tile / NTL, ntl = tile % NTL;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(16 * mt + 4 * (lane >> 4) + r) * N + 16 * ntl + (lane & 15)] = acc[i][r];
+        }
+    }
+}
+
+// Sum the per-block partials in block order and add into the gradients.
+__global__ __launch_bounds__(256) void k_wgrad_apply(const float *partials, BackwardBufs bb)
+{
+    const int64_t P0 = 0, P1 = P0 + (int64_t)kWgBlocks * 128 * 48, P2 = P1 + (int64_t)kWgBlocks * 128 * 128,
+                  P3 = P2 + (int64_t)kWgBlocks * 16 * 128, P4 = P3 + (int64_t)kWgBlocks * 128 * 16;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    auto sum = [&](int64_t base, int mn, int idx) {
+        float s = 0.f;
+        for (int blk = 0; blk < kWgBlocks; ++blk) s += partials[base + (int64_t)blk * mn + idx];
+        return s;
+    };
+    if (e < 128 * 39) {                       // dW0
+        const int o = e / 39, i = e % 39;
+        bb.d_w0[e] += sum(P0, 128 * 48, o * 48 + i);
+    } else if (e < 128 * 39 + 128) {          // db0 (constant-1 column)
+        const int o = e - 128 * 39;
+        bb.d_b0[o] += sum(P0, 128 * 48, o * 48 + 39);
+    } else if (e < 128 * 39 + 128 + 128 * 128) {   // dW1
+        const int k = e - (128 * 39 + 128);
+        bb.d_w1[k] += sum(P1, 128 * 128, k);
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128) {   // dW2
+        const int k = e - (128 * 39 + 128 + 128 * 128);
+        bb.d_w2[k] += sum(P2, 16 * 128, k);
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128) {   // db1 = dp1^T [x|1] column 39
+        const int o = e - (128 * 39 + 128 + 128 * 128 + 3 * 128);
+        bb.d_b1[o] += sum(P3, 128 * 16, o * 16 + 7);
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3) {   // db2
+        const int ch = e - (128 * 39 + 128 + 128 * 128 + 3 * 128 + 128);
+        bb.d_b2[ch] += sum(P4, 16 * 16, ch * 16 + 7);
+    }
+}
+
+void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
+{
+    // slab per block from the pass's maximum sample count
+    const int64_t max_s = b.n * (int64_t)b.n_samples;
+    const int64_t slab = ((max_s + kWgBlocks - 1) / kWgBlocks + kWgStep - 1) / kWgStep * kWgStep;
+    const uint32_t *tot = b.offsets + b.n;
+    float *P = bb.partials;
+    const int64_t P1 = (int64_t)kWgBlocks * 128 * 48, P2 = P1 + (int64_t)kWgBlocks * 128 * 128,
+                  P3 = P2 + (int64_t)kWgBlocks * 16 * 128, P4 = P3 + (int64_t)kWgBlocks * 128 * 16;
+    const dim3 grid(kWgBlocks), blk(256);
+    hipLaunchKernelGGL((k_wgrad<128, 48>), grid, blk, 0, s, b.stage, tot, kStDP0, kStX, P, slab);
+    hipLaunchKernelGGL((k_wgrad<128, 128>), grid, blk, 0, s, b.stage, tot, kStDP1, kStH1, P + P1, slab);
+    hipLaunchKernelGGL((k_wgrad<16, 128>), grid, blk, 0, s, b.stage, tot, kStDL, kStH2, P + P2, slab);
+    hipLaunchKernelGGL((k_wgrad<128, 16>), grid, blk, 0, s, b.stage, tot, kStDP1, kStX + 32, P + P3, slab);
+    hipLaunchKernelGGL((k_wgrad<16, 16>), grid, blk, 0, s, b.stage, tot, kStDL, kStX + 32, P + P4, slab);
+    const int n_out = 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3;
+    hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + 255) / 256), dim3(256), 0, s, (const float *)P, bb);
+}
+
+}  // namespace cic

@@ -30,6 +30,9 @@ struct RenderBufs {
     uint16_t *rec_k;       // [n*N] its sample index
     float *rec_w;          // [n*N] its weight
     float *rec_c;          // [n*N*3] MLP colour per live sample
+    float *slot_t;         // [n*N] transmittance T_k of live samples (adjoint only; nullable)
+    float *rec_t;          // [n*N] compacted T_k (adjoint only; nullable)
+    float *stage;          // [n*N][kStageStride] per-sample MLP vectors (adjoint only; nullable)
     // voxel order
     uint32_t *rec_key;     // [n*N] brick of each live sample
     uint32_t *brick_off;   // [n_bricks+1] counts, then cursors
@@ -37,6 +40,13 @@ struct RenderBufs {
     uint32_t *perm;        // [n*N] sample order for the MLP stage
     int64_t n_bricks;
 };
+
+// Per-sample row of MLP vectors kept for the weight gradients (adjoint):
+// inputs with a constant 1 in the padding slot (so the bias gradient falls
+// out of the same product), both hidden activations, both hidden-layer
+// pre-activation gradients and the output-logit gradient.
+constexpr int kStX = 0, kStH1 = 40, kStH2 = 168, kStDP0 = 296, kStDP1 = 424, kStDL = 552;
+constexpr int kStageStride = 568;   // the logit-gradient block is 16 wide (3 used, rest zero)
 
 // scan.hip
 size_t scan_tmp_elems(int64_t n);
@@ -62,6 +72,8 @@ void launch_build_occupancy(const GridK &g, float thr, uint8_t *occ, hipStream_t
 int mlp_lds_bytes(int compute);
 template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
+// forward with per-sample staging of x, h1, h2 (float32 grids, ray order)
+void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s);
 
 // warp.hip
 void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], const float *ref_rgb,
@@ -75,17 +87,14 @@ struct BackwardBufs {
     float *d_density, *d_features;
     float *d_w0, *d_b0, *d_w1, *d_b1, *d_w2, *d_b2;
     float *rec_dc;         // [n*N*3] dL/dc per live sample
-    float *stage;          // [n*N][kStageStride] per-sample vectors for the weight gradients
-    float *partials;       // [n_part][kParamCount] per-block weight-gradient partials
-    int64_t n_part_max;
+    float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
 };
-constexpr int kStageX = 40, kStageH = 128;
-constexpr int kStageStride = kStageX + 4 * kStageH + 4;   // x | h1 | h2 | dp0 | dp1 | dlogit
-constexpr int kParamCount = 128 * 39 + 128 + 128 * 128 + 128 + 3 * 128 + 3;
-template <typename T>
+constexpr int kWgBlocks = 256;
+// per-block partial products: dp0^T[x|1] (128x48), dp1^T h1 (128x128),
+// dl^T h2 (16x128), dp1^T ones (128x16), dl^T ones (16x16)
+constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 * 16;
 void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
                                hipStream_t s);
-template <typename T>
 void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb,
                          hipStream_t s);
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);

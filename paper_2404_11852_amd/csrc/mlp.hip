@@ -111,7 +111,9 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
     }
 }
 
-template <typename T>
+// STAGE: also write x (with the constant-1 slot), h1 and h2 of every sample
+// to its stage row for the adjoint's weight gradients.
+template <typename T, bool STAGE>
 __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
     extern __shared__ float lds[];
@@ -137,6 +139,14 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             if (valid[nt]) {
                 sample_inputs<T>(g, b, rec[nt], q, x[nt]);
+                if (STAGE) {
+                    float *row = b.stage + rec[nt] * kStageStride + kStX;
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) {
+                        const int src = l0_input(c, q);
+                        row[src >= 0 ? src : 39] = src >= 0 ? x[nt][c] : 1.0f;
+                    }
+                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 10; ++c) x[nt][c] = 0.f;
@@ -178,6 +188,14 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             for (int nt = 0; nt < kNT; ++nt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) h1[t][nt][r] = fmaxf(h1[t][nt][r], 0.f);
+        if (STAGE) {
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+                if (valid[nt])
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        *(f4_t *)(b.stage + rec[nt] * kStageStride + kStH1 + 16 * t + 4 * q) = h1[t][nt];
+        }
 
         // layer 1: 128 -> 128
         f4_t h2[8][kNT];
@@ -207,6 +225,18 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             }
         }
 
+        if (STAGE) {
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+                if (valid[nt])
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        f4_t v = h2[t][nt];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+                        *(f4_t *)(b.stage + rec[nt] * kStageStride + kStH2 + 16 * t + 4 * q) = v;
+                    }
+        }
         // layer 2: 128 -> 3 on the vector ALUs, then sigmoid
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
@@ -246,16 +276,29 @@ static int num_cus()
     return n > 0 ? n : 256;
 }
 
-template <typename T>
-void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+template <typename T, bool STAGE>
+static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
     const int lds = mlp_lds_bytes(m.compute);
     static bool attr_set = false;   // per process; the attribute is per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T, STAGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_mlp_fwd_f32<T>, dim3(num_cus()), dim3(kMlpWaves * 64), lds, s, g, m, b, voxel ? 1 : 0);
+    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE>), dim3(num_cus()), dim3(kMlpWaves * 64), lds, s, g, m, b,
+                       voxel ? 1 : 0);
+}
+
+template <typename T>
+void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+{
+    launch_fwd<T, false>(g, m, b, voxel, s);
+}
+
+void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s)
+{
+    launch_fwd<float, true>(g, m, b, false, s);
 }
 template void launch_mlp_forward<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
 template void launch_mlp_forward<__half>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);

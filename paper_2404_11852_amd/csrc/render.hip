@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
             const uint32_t pos = count + (uint32_t)__popcll(lmask & lanes_below_mask());
             slot_k[pos] = (uint16_t)k;
             slot_w[pos] = w;
+            if (b.slot_t) b.slot_t[ray * (int64_t)N + pos] = Tk;
         }
         count += (uint32_t)__popcll(lmask);
         depth += wave_sum(w * tk);
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxe
             b.rec_ray[off + j] = (uint32_t)ray;
             b.rec_k[off + j] = k;
             b.rec_w[off + j] = b.slot_w[ray * (int64_t)N + j];
+            if (b.rec_t) b.rec_t[off + j] = b.slot_t[ray * (int64_t)N + j];
             if (voxel) {
                 int i0[3];
                 float fr[3], tk;
