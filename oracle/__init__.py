@@ -39,7 +39,7 @@ class MLP(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("out_dim", C.c_int32),
                 ("pe_freqs", C.c_int32),
                 ("w0", C.c_void_p), ("b0", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_void_p),
-                ("w2", C.c_void_p), ("b2", C.c_void_p)]
+                ("w2", C.c_void_p), ("b2", C.c_void_p), ("round_bf16", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -74,7 +74,7 @@ class Model:
     """Holds contiguous arrays plus the ctypes structs that point at them."""
 
     def __init__(self, density, features, mlp, box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3,
-                 density_shift=0.0, occ=None, pe_freqs=4):
+                 density_shift=0.0, occ=None, pe_freqs=4, round_bf16=False):
         self.density = _f32(density)
         self.features = _f32(features)
         res = self.density.shape
@@ -90,7 +90,8 @@ class Model:
         assert in_dim == n_feat + 3 + 6 * pe_freqs
         assert in_dim <= 256 and hidden <= 1024 and n_feat <= 64 and out_dim <= 8
         self.mlp = MLP(in_dim, hidden, out_dim, pe_freqs,
-                       *[_p(self.w[k]).value for k in ("w0", "b0", "w1", "b1", "w2", "b2")])
+                       *[_p(self.w[k]).value for k in ("w0", "b0", "w1", "b1", "w2", "b2")],
+                       int(bool(round_bf16)))
 
     def set_occupancy(self, occ):
         self.occ = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)

@@ -65,6 +65,9 @@ typedef struct {
     const float *w0, *b0;    /* [hidden][in_dim], [hidden] */
     const float *w1, *b1;    /* [hidden][hidden], [hidden] */
     const float *w2, *b2;    /* [out_dim][hidden], [out_dim] */
+    int32_t round_bf16;      /* 1: each layer's inputs and weights rounded to
+                                bfloat16 (round to nearest even) before the
+                                float64 products (the precision path) */
 } orc_mlp;
 
 typedef struct {
@@ -199,6 +202,29 @@ static void mlp_input(const orc_mlp *m, int n_feat, const double *feat, const fl
         }
 }
 
+/* Round to bfloat16 (8-bit significand), nearest-even, via float32. */
+static double bf16_round(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return v;   /* inf / nan unchanged */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double wt(const orc_mlp *m, const float *w, int64_t i)
+{
+    return m->round_bf16 ? bf16_round((double)w[i]) : (double)w[i];
+}
+
+static double act(const orc_mlp *m, double v)
+{
+    return m->round_bf16 ? bf16_round(v) : v;
+}
+
 /* Two ReLU hidden layers and a sigmoid output layer; h1, h2 keep the
  * post-activation values, c the output. */
 static void mlp_forward(const orc_mlp *m, const double *x, double *h1, double *h2, double *c)
@@ -206,17 +232,17 @@ static void mlp_forward(const orc_mlp *m, const double *x, double *h1, double *h
     int I = m->in_dim, H = m->hidden, O = m->out_dim;
     for (int o = 0; o < H; ++o) {
         double s = m->b0[o];
-        for (int i = 0; i < I; ++i) s += (double)m->w0[(int64_t)o * I + i] * x[i];
+        for (int i = 0; i < I; ++i) s += wt(m, m->w0, (int64_t)o * I + i) * act(m, x[i]);
         h1[o] = s > 0.0 ? s : 0.0;
     }
     for (int o = 0; o < H; ++o) {
         double s = m->b1[o];
-        for (int i = 0; i < H; ++i) s += (double)m->w1[(int64_t)o * H + i] * h1[i];
+        for (int i = 0; i < H; ++i) s += wt(m, m->w1, (int64_t)o * H + i) * act(m, h1[i]);
         h2[o] = s > 0.0 ? s : 0.0;
     }
     for (int o = 0; o < O; ++o) {
         double s = m->b2[o];
-        for (int i = 0; i < H; ++i) s += (double)m->w2[(int64_t)o * H + i] * h2[i];
+        for (int i = 0; i < H; ++i) s += wt(m, m->w2, (int64_t)o * H + i) * act(m, h2[i]);
         c[o] = sigmoid_d(s);
     }
 }

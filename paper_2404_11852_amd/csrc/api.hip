@@ -70,7 +70,8 @@ int check_grid(const cic_grid *g)
 int check_mlp(const cic_mlp *m)
 {
     if (!m) return fail(CIC_ERR_INVALID, "mlp is NULL");
-    if (m->compute != CIC_F32) return fail(CIC_ERR_INVALID, "mlp.compute=%d is not supported", m->compute);
+    if (m->compute != CIC_F32 && m->compute != CIC_BF16)
+        return fail(CIC_ERR_INVALID, "mlp.compute=%d is not CIC_F32 or CIC_BF16", m->compute);
     if (m->in_dim != 39 || m->hidden != 128 || m->pe_freqs != 4)
         return fail(CIC_ERR_INVALID, "mlp shape in_dim=%d hidden=%d pe_freqs=%d; supported 39/128/4", m->in_dim,
                     m->hidden, m->pe_freqs);
@@ -548,6 +549,7 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
     if (grid->storage != CIC_F32) return fail(CIC_ERR_INVALID, "render_backward needs a float32 grid");
+    if (mlp->compute != CIC_F32) return fail(CIC_ERR_INVALID, "render_backward needs CIC_F32 compute");
     if (n_rays < 0) return fail(CIC_ERR_INVALID, "n_rays < 0");
     if (n_rays == 0) return ok();
     if (!rays_o || !rays_d || !d_rgb) return fail(CIC_ERR_INVALID, "rays or d_rgb is NULL");

@@ -268,6 +268,210 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 variant: every layer on v_mfma_f32_16x16x32_bf16 (inputs rounded to
+// BF16 with round-to-nearest-even, FP32 accumulation, FP32 bias and
+// activations).  K = 32 per instruction: lane (q, j) supplies 8 consecutive
+// reduction slots.  Layer 0 uses two K-chunks (64 slots >= 39 inputs, same
+// per-lane input assignment as the FP32 kernel: the ten values of lane group
+// q fill chunk 0 and the first two slots of chunk 1).  Layers 1 and 2 take
+// their B operand from two consecutive 16-row result tiles of the previous
+// layer: chunk c of lane group q covers rows 32c + 4q + (0..3) and
+// 32c + 16 + 4q + (0..3), and the weight fragments are laid out to match.
+// The 3-wide output layer is one zero-padded 16-row tile.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kBfWaves = 4;
+constexpr int kBfNT = 2;
+constexpr int kBfBatch = 16 * kBfNT;
+// LDS layout in 16-byte fragments, then floats
+constexpr int kBfW0 = 0;                           // [t 8][c 2][lane 64]
+constexpr int kBfW1 = kBfW0 + 8 * 2 * 64;          // [t 8][c 4][lane 64]
+constexpr int kBfW2 = kBfW1 + 8 * 4 * 64;          // [c 4][lane 64]
+constexpr int kBfFrags = kBfW2 + 4 * 64;
+constexpr int kBfB0 = 0, kBfB1 = 128, kBfB2 = 256, kBfFloats = 260;
+constexpr int kLdsBf16 = kBfFrags * 16 + kBfFloats * 4;
+
+// reduction index of slot e of chunk c for lane group q in layers 1 and 2
+__host__ __device__ __forceinline__ int hid_k(int c, int q, int e)
+{
+    return e < 4 ? 32 * c + 4 * q + e : 32 * c + 16 + 4 * q + (e - 4);
+}
+
+// input index of slot e of chunk c for lane group q in layer 0 (-1 = pad)
+__host__ __device__ __forceinline__ int bf_l0_input(int c, int q, int e)
+{
+    const int slot = 8 * c + e;
+    return slot < 10 ? l0_input(slot, q) : -1;
+}
+
+__device__ void stage_weights_bf16(const cic_mlp &m, bf8_t *frag, float *fl)
+{
+    const int nt = blockDim.x;
+    for (int i = threadIdx.x; i < 8 * 2 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) & 1, t = i >> 7;
+        const int row = 16 * t + (l & 15), q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int src = bf_l0_input(c, q, e);
+            v[e] = (__bf16)(src >= 0 ? m.w0[row * 39 + src] : 0.f);
+        }
+        frag[kBfW0 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 8 * 4 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) & 3, t = i >> 8;
+        const int row = 16 * t + (l & 15), q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)m.w1[row * 128 + hid_k(c, q, e)];
+        frag[kBfW1 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 4 * 64; i += nt) {
+        const int l = i & 63, c = i >> 6;
+        const int row = l & 15, q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)(row < 3 ? m.w2[row * 128 + hid_k(c, q, e)] : 0.f);
+        frag[kBfW2 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 128; i += nt) {
+        fl[kBfB0 + i] = m.b0[i];
+        fl[kBfB1 + i] = m.b1[i];
+    }
+    if (threadIdx.x < 4) fl[kBfB2 + threadIdx.x] = threadIdx.x < 3 ? m.b2[threadIdx.x] : 0.f;
+}
+
+__device__ __forceinline__ bf8_t pack_bf8(const f4_t a, const f4_t b)
+{
+    bf8_t v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = (__bf16)a[e];
+        v[4 + e] = (__bf16)b[e];
+    }
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
+{
+    extern __shared__ float lds_raw[];
+    bf8_t *frag = (bf8_t *)lds_raw;
+    float *fl = lds_raw + kBfFrags * 4;
+    stage_weights_bf16(m, frag, fl);
+    __syncthreads();
+
+    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+    const int wave = threadIdx.x / 64;
+    const int64_t total = (int64_t)b.offsets[b.n];
+    const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
+
+    for (int64_t bt = (int64_t)blockIdx.x * kBfWaves + wave; bt < nbatch; bt += (int64_t)gridDim.x * kBfWaves) {
+        bf8_t xin[kBfNT][2];
+        int64_t rec[kBfNT];
+        bool valid[kBfNT];
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) {
+            const int64_t s = bt * kBfBatch + nt * 16 + j;
+            valid[nt] = s < total;
+            rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
+            float x[10];
+            if (valid[nt]) {
+                sample_inputs<T>(g, b, rec[nt], q, x);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 10; ++c) x[c] = 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                xin[nt][0][e] = (__bf16)x[e];
+                xin[nt][1][e] = (__bf16)(e < 2 ? x[8 + e] : 0.f);
+            }
+        }
+        // layer 0
+        f4_t h1[8][kBfNT];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f4_t bias = *(const f4_t *)(fl + kBfB0 + 16 * t + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) h1[t][nt] = bias;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kBfNT; ++nt)
+                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], h1[t][nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        bf8_t hb[4][kBfNT];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) {
+                f4_t lo = h1[2 * c][nt], hi = h1[2 * c + 1][nt];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    lo[r] = fmaxf(lo[r], 0.f);
+                    hi[r] = fmaxf(hi[r], 0.f);
+                }
+                hb[c][nt] = pack_bf8(lo, hi);
+            }
+        // layer 1
+        f4_t h2[8][kBfNT];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f4_t bias = *(const f4_t *)(fl + kBfB1 + 16 * t + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) h2[t][nt] = bias;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bf8_t a = frag[kBfW1 + (t * 4 + c) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kBfNT; ++nt)
+                    h2[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][nt], h2[t][nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2 (one zero-padded tile)
+        f4_t o3[kBfNT];
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) o3[nt] = *(const f4_t *)(fl + kBfB2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bf8_t a = frag[kBfW2 + c * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) {
+                f4_t lo = h2[2 * c][nt], hi = h2[2 * c + 1][nt];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    lo[r] = fmaxf(lo[r], 0.f);
+                    hi[r] = fmaxf(hi[r], 0.f);
+                }
+                o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_bf8(lo, hi), o3[nt], 0, 0, 0);
+            }
+        }
+        // lanes of group 0 hold rows 0..3 (colour channels 0..2) of their sample
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) {
+            if (valid[nt] && q == 0) {
+                float *out = b.rec_c + 3 * rec[nt];
+                out[0] = sigmoidf(o3[nt][0]);
+                out[1] = sigmoidf(o3[nt][1]);
+                out[2] = sigmoidf(o3[nt][2]);
+            }
+        }
+    }
+}
+
 static int num_cus()
 {
     int dev = 0, n = 0;
@@ -293,6 +497,17 @@ static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bo
 template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
+    if (m.compute == CIC_BF16) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      kLdsBf16);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(k_mlp_fwd_bf16<T>, dim3(num_cus() * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
+                           voxel ? 1 : 0);
+        return;
+    }
     launch_fwd<T, false>(g, m, b, voxel, s);
 }
 

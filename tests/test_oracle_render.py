@@ -341,3 +341,28 @@ def test_occupancy_skip_error_bound(orc):
     L = np.where(tn < tf, tf - tn, 0.0)
     bound = 2 * 1e-2 * L + 1e-12
     assert np.all(np.abs(a - b).max(1) <= bound)
+
+
+def test_bf16_mode_matches_torch_bfloat16(orc):
+    """Precision mode: every layer's inputs and weights rounded to bfloat16
+    (round to nearest even) with float64 accumulation equals torch's
+    bfloat16 conversion followed by float64 Linear/ReLU/Sigmoid."""
+    import torch
+    mlp = synth.make_mlp(11, bias_std=0.2)
+    m = orc.Model(np.zeros((2, 2, 2), np.float32), np.zeros((2, 2, 2, 12), np.float32), mlp, round_bf16=True)
+    x = np.random.default_rng(12).standard_normal((128, 39)) * 2.0
+    got = orc.mlp_forward(m, x)
+
+    def r(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    with torch.no_grad():
+        h = torch.from_numpy(x)
+        for k, act in (("0", torch.relu), ("1", torch.relu), ("2", torch.sigmoid)):
+            w = r(torch.from_numpy(mlp["w" + k]))
+            b = torch.from_numpy(mlp["b" + k].astype(np.float64))
+            h = act(r(h) @ w.T + b)
+    np.testing.assert_allclose(got, h.numpy(), rtol=0, atol=1e-13)
+    # and it is a different function from the float64 one
+    m64 = orc.Model(np.zeros((2, 2, 2), np.float32), np.zeros((2, 2, 2, 12), np.float32), mlp)
+    assert np.abs(orc.mlp_forward(m64, x) - got).max() > 1e-4
