@@ -7,8 +7,9 @@ to 256 samples per ray, occupancy skipping, early termination at 1e-4)
 through render_frame; value = evaluated ray samples per second (samples that
 pass through the MLP), inputs resident in HBM.  After the timed region the
 same JSON line reports the other measured forms as sub-objects: the 32-frame
-SpaRW orbit (FPS, mask fraction, PSNR against full renders), and the
-per-stage times.  The roofline object is for the dominant kernel (the
+SpaRW orbit (FPS, mask fraction, PSNR against full renders), the precision
+path (8 views in one call, FP16 grid + BF16 MLP, against FP32 on the same
+rays), the fwd+bwd training step, and the per-stage times.  The roofline object is for the dominant kernel (the
 feature-gather + MLP stage), timed with HIP events on its launch stream.
 The CPU baseline is the plain oracle on a bounded, seeded pixel sample.
 
@@ -147,6 +148,113 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16):
     }
 
 
+def precision_bench(scene, occ, steps):
+    """Eight 800x800 views on the radius-4 sphere in one render_rays call:
+    FP16 grids + BF16 MLP against the FP32 path on the same rays."""
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    dens, feats, mlp = scene
+    W = H = 800
+    g16 = cic.Model(dens, feats, mlp, device="cuda:0", storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
+                    compute=cic.CIC_BF16)
+    g16.set_occupancy(occ)
+    g32 = cic.Model(dens, feats, mlp, device="cuda:0", density_shift=synth.DENSITY_SHIFT)
+    g32.set_occupancy(occ)
+    f, cx, cy = synth.intrinsics(W, H)
+    rays = [cic.generate_rays(cic.make_camera(W, H, f, cx, cy, synth.as_f32(p))) for p in synth.sphere_poses(8, 2)]
+    o = torch.cat([r[0] for r in rays]).contiguous()
+    d = torch.cat([r[1] for r in rays]).contiguous()
+    go = cic.make_opts(256, 1e-4, True)
+    out = {}
+    imgs = {}
+    for name, model in (("bf16", g16), ("fp32", g32)):
+        cic.render_rays(model, go, o, d)
+        n_eval = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        torch.cuda.synchronize()
+        _lib.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rgb, _, _ = cic.render_rays(model, go, o, d, n_eval=n_eval)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = _lib.timing_read()
+        _lib.timing_enable(False)
+        imgs[name] = rgb
+        ne = int(n_eval.item()) / steps
+        out[name] = {"samples_per_s": ne * steps / (t1 - t0), "ms_per_launch": 1e3 * (t1 - t0) / steps,
+                     "fps_800x800_per_view": 8 * steps / (t1 - t0), "evaluated_samples": ne,
+                     "stage_ms": {k: v[0] / steps for k, v in st.items() if v[1]}}
+    out["speedup_bf16_vs_fp32"] = out["bf16"]["samples_per_s"] / out["fp32"]["samples_per_s"]
+    out["psnr_bf16_vs_fp32_gpu_db"] = psnr(imgs["bf16"], imgs["fp32"])
+    out["max_abs_bf16_vs_fp32_gpu"] = float((imgs["bf16"] - imgs["fp32"]).abs().max().item())
+    mlp_ms = out["bf16"]["stage_ms"].get("mlp", 0.0)
+    if mlp_ms > 0:
+        ach = MLP_FLOP_PER_SAMPLE * out["bf16"]["evaluated_samples"] / (mlp_ms * 1e-3) / 1e12
+        out["bf16_mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
+                                    "frac": ach / 2500.0}
+    out["workload"] = "8 views x 800x800 (5.12M rays, one call), 160^3 grid, 256 samples, skip + termination"
+    return out
+
+
+def fwd_bwd_bench(steps):
+    """One MSE training step (forward + adjoint) on 8192 rays drawn from 8
+    views of a hidden scene; model grids N(0, 0.01), FP32."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    ex = synth.get_config("cfg5").extra
+    W = H = 800
+    f, cx, cy = synth.intrinsics(W, H)
+    poses = synth.sphere_poses(8, seed=3)
+    view, pix = synth.training_pixels(8, W, H, 8192, seed=ex["ray_seed"])
+    o = torch.empty((8192, 3), device="cuda:0")
+    d = torch.empty((8192, 3), device="cuda:0")
+    for v in range(8):
+        sel = torch.from_numpy(np.nonzero(view == v)[0]).cuda()
+        oo, dd = cic.generate_rays(cic.make_camera(W, H, f, cx, cy, synth.as_f32(poses[v])),
+                                   torch.from_numpy(pix[view == v]))
+        o[sel], d[sel] = oo, dd
+    gd, gf = synth.make_scene(160, seed=ex["gt_scene_seed"])
+    gt_model = cic.Model(gd, gf, synth.make_mlp(ex["gt_mlp_seed"]), device="cuda:0",
+                         density_shift=synth.DENSITY_SHIFT)
+    go = cic.make_opts(256, 1e-4)
+    target, _, _ = cic.render_rays(gt_model, go, o, d)
+    md, mf = synth.make_model_grid(160, seed=ex["model_grid_seed"])
+    model = cic.Model(md, mf, synth.make_mlp(ex["model_mlp_seed"]), device="cuda:0",
+                      density_shift=synth.DENSITY_SHIFT)
+    grads = {"density": torch.zeros_like(model.density), "features": torch.zeros_like(model.features)}
+    for k, v in model.w.items():
+        grads[k] = torch.zeros_like(v)
+
+    def step(n_eval=None):
+        for g in grads.values():
+            g.zero_()
+        rgb, _, _ = cic.render_rays(model, go, o, d, n_eval=n_eval)
+        d_rgb = (2.0 / rgb.numel()) * (rgb - target)
+        cic.render_backward(model, go, o, d, d_rgb, grads=grads)
+
+    step()
+    n_eval = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(n_eval)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = _lib.timing_read()
+    _lib.timing_enable(False)
+    ne = int(n_eval.item()) / steps
+    return {"samples_per_s": ne * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "evaluated_samples_per_step": ne,
+            "stage_ms_per_step": {k: v[0] / steps for k, v in st.items() if v[1]},
+            "workload": "8192 rays from 8 views, 160^3 model grids N(0,0.01), 256 samples, fwd + adjoint, FP32"}
+
+
 def cpu_baseline(scene, target_s=12.0):
     """The oracle, as it stands, on a seeded pixel sample of the same frame."""
     import numpy as np
@@ -186,6 +294,8 @@ def main():
     ap.add_argument("--order", choices=["ray", "voxel"], default="ray")
     ap.add_argument("--skip-sparw", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-precision", action="store_true")
+    ap.add_argument("--skip-fwd-bwd", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -251,6 +361,12 @@ def main():
     if not args.skip_sparw:
         log("SpaRW orbit")
         out["sparw"] = sparw_orbit(model, opts, W, H)
+    if not args.skip_precision:
+        log("precision path (8 views, FP16 grid + BF16 MLP)")
+        out["precision"] = precision_bench(scene, model.occupancy, max(3, args.steps // 4))
+    if not args.skip_fwd_bwd:
+        log("fwd+bwd training step")
+        out["fwd_bwd"] = fwd_bwd_bench(max(3, args.steps // 2))
     if not args.skip_cpu:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(scene)
