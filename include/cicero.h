@@ -221,8 +221,10 @@ enum {
     CIC_STAGE_REDUCE = 3,     /* per-ray accumulation */
     CIC_STAGE_WARP = 4,       /* z-buffer splat + resolve */
     CIC_STAGE_RAYGEN = 5,     /* pixel rays */
-    CIC_STAGE_BACKWARD = 6,   /* adjoint kernels */
-    CIC_STAGE_COUNT = 7
+    CIC_STAGE_BACKWARD = 6,   /* adjoint: compositing adjoint + density scatter */
+    CIC_STAGE_BWD_MLP = 7,    /* adjoint: MLP backward + feature scatter */
+    CIC_STAGE_BWD_WGRAD = 8,  /* adjoint: weight-gradient products */
+    CIC_STAGE_COUNT = 9
 };
 int cic_timing_enable(int on);
 int cic_timing_read(double *ms, int64_t *launches, int n_stages);

@@ -597,7 +597,13 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         {
             StageTimer t(CIC_STAGE_BACKWARD, s);
             launch_backward_composite(gk, ok_, b, bb, s);
+        }
+        {
+            StageTimer t(CIC_STAGE_BWD_MLP, s);
             launch_mlp_backward(gk, *mlp, b, bb, s);
+        }
+        {
+            StageTimer t(CIC_STAGE_BWD_WGRAD, s);
             launch_weight_grads(b, bb, s);
         }
     }

@@ -26,8 +26,14 @@ namespace cic {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef float f2_t __attribute__((ext_vector_type(2)));
 
-constexpr int kMlpWaves = 8;
-constexpr int kNT = 2;   // 16-sample tiles per wavefront batch
+// 16-sample tiles per wavefront batch; one tile keeps a wavefront under 128
+// VGPRs, so the 16 wavefronts of the CU's single workgroup (the weights take
+// 88 KB of LDS) give four per SIMD to overlap gathers with MFMA work.
+#ifndef CIC_F32_NT
+#define CIC_F32_NT 1
+#endif
+constexpr int kNT = CIC_F32_NT;
+constexpr int kMlpWaves = kNT == 1 ? 16 : 8;
 constexpr int kBatch = 16 * kNT;
 
 // float32 LDS layout (in floats)
@@ -161,26 +167,25 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) h1[t][nt] = bias;
         }
-        // A fragments are software-pipelined one step ahead; the scheduling
-        // barrier keeps the compiler from hoisting every LDS read (which
-        // would exceed the register file).
-        {
-            f2_t a = w0f[lane];
+        // Layer 0: per input chunk pair, the eight output tiles' A fragments
+        // are read together and the MFMAs alternate between the eight
+        // independent accumulators.  The scheduling barriers keep the
+        // compiler from hoisting every LDS read (which would exceed the
+        // register budget).
 #pragma unroll
-            for (int c2 = 0; c2 < 5; ++c2) {
+        for (int c2 = 0; c2 < 5; ++c2) {
+            f2_t a[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int nx = (c2 * 8 + t + 1 < 40) ? (c2 * 8 + t + 1) : (c2 * 8 + t);
-                    const f2_t an = w0f[((nx % 8) * 5 + nx / 8) * 64 + lane];
+            for (int t = 0; t < 8; ++t) a[t] = w0f[(t * 5 + c2) * 64 + lane];
 #pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt) {
-                        h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x[nt][2 * c2], h1[t][nt], 0, 0, 0);
-                        h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x[nt][2 * c2 + 1], h1[t][nt], 0, 0, 0);
-                    }
-                    a = an;
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][e], x[nt][2 * c2 + e], h1[t][nt], 0, 0,
+                                                                          0);
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t)
@@ -205,21 +210,31 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) h2[t][nt] = bias;
         }
+        // Layer 1: groups of four output tiles; the next group's fragments
+        // are read while the current group's 16 MFMAs (four independent
+        // accumulators, one per tile) run.
         {
-            f4_t a = w1f[lane];
+            f4_t a[4], an[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) a[tt] = w1f[(tt * 8 + 0) * 64 + lane];
 #pragma unroll
             for (int c4 = 0; c4 < 8; ++c4) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int nx = (c4 * 8 + t + 1 < 64) ? (c4 * 8 + t + 1) : (c4 * 8 + t);
-                    const f4_t an = w1f[((nx % 8) * 8 + nx / 8) * 64 + lane];
+                for (int tg = 0; tg < 2; ++tg) {
+                    const int step = c4 * 2 + tg, nx = step + 1 < 16 ? step + 1 : step;
+                    const int nc4 = nx >> 1, ntg = nx & 1;
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) an[tt] = w1f[((4 * ntg + tt) * 8 + nc4) * 64 + lane];
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                        for (int nt = 0; nt < kNT; ++nt)
-                            h2[t][nt] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], h1[c4][nt][rr], h2[t][nt], 0, 0, 0);
-                    a = an;
+                        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                            for (int nt = 0; nt < kNT; ++nt)
+                                h2[4 * tg + tt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    a[tt][rr], h1[c4][nt][rr], h2[4 * tg + tt][nt], 0, 0, 0);
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) a[tt] = an[tt];
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }

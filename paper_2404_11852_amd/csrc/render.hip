@@ -239,27 +239,39 @@ void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
 }
 
-// Per-ray accumulation: rgb = sum_k w_k c_k (in sample order) + T_stop bg,
-// depth_t, acc = 1 - T_stop; frame mode converts to z-depth with the void
-// rule.  One thread per ray.
+// Per-ray accumulation: rgb = sum_k w_k c_k + T_stop bg, depth_t,
+// acc = 1 - T_stop; frame mode converts to z-depth with the void rule.  One
+// wavefront per ray: lanes read consecutive live samples (coalesced) and a
+// butterfly sum combines them in a fixed order, so the result does not
+// depend on the order in which the MLP stage produced the colours.
 __global__ __launch_bounds__(256) void k_reduce(RenderBufs b, OptsK op, float *rgb, float *depth, float *acc,
                                                 const int32_t *out_map, cic_camera cam, int frame,
                                                 unsigned long long *n_eval)
 {
-    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
+    if (n_eval && ray == 0 && lane == 0) atomicAdd(n_eval, (unsigned long long)b.offsets[b.n]);
+    if (ray >= b.n) return;
     const uint32_t n_act = b.n_active ? *b.n_active : (uint32_t)b.n;
-    if (n_eval && ray == 0) atomicAdd(n_eval, (unsigned long long)b.offsets[b.n]);
-    if (ray >= b.n || (uint64_t)ray >= n_act) return;
+    if ((uint64_t)ray >= n_act) return;
     const uint32_t cnt = b.count[ray], off = b.offsets[ray];
-    const RayInfo inf = b.info[ray];
     float r = 0.f, gg = 0.f, bb = 0.f;
-    for (uint32_t j = 0; j < cnt; ++j) {
-        const float w = b.rec_w[off + j];
-        const float *c = b.rec_c + 3 * (int64_t)(off + j);
-        r = fmaf(w, c[0], r);
-        gg = fmaf(w, c[1], gg);
-        bb = fmaf(w, c[2], bb);
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+        const uint32_t j = j0 + lane;
+        float pr = 0.f, pg = 0.f, pb = 0.f;
+        if (j < cnt) {
+            const int64_t k = (int64_t)off + j;
+            const float w = b.rec_w[k];
+            pr = w * b.rec_c[3 * k];
+            pg = w * b.rec_c[3 * k + 1];
+            pb = w * b.rec_c[3 * k + 2];
+        }
+        r += wave_sum(pr);
+        gg += wave_sum(pg);
+        bb += wave_sum(pb);
     }
+    if (lane != 0) return;
+    const RayInfo inf = b.info[ray];
     const float ts = inf.t_stop;
     const int64_t out = out_map ? (int64_t)out_map[ray] : ray;
     rgb[3 * out + 0] = fmaf(ts, op.bg[0], r);
@@ -283,7 +295,7 @@ __global__ __launch_bounds__(256) void k_reduce(RenderBufs b, OptsK op, float *r
 void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,
                    const int32_t *out_map, const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s)
 {
-    const int64_t blocks = (b.n + 255) / 256;
+    const int64_t blocks = (b.n + kRayWaves - 1) / kRayWaves;
     cic_camera cam{};
     if (frame_cam) cam = *frame_cam;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, b, o, rgb, depth, acc,
