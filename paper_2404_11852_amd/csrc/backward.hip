@@ -292,113 +292,141 @@ void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, 
 }
 
 // ---------------------------------------------------------------------------
-// weight gradients: out[o][i] = sum_s A[s][a_col + o] * B[s][b_col + i] over
-// the staged rows, split over kWgBlocks blocks (each a contiguous range of
-// samples), one partial matrix per block
+// Weight gradients: sums over samples of outer products of staged vectors,
+//   P0 = dp0^T [x|1|h1[0:8]]   (128 x 48: dW0 and, in column 39, db0)
+//   P1 = dp1^T h1              (128 x 128: dW1)
+//   P2 = dl^T h2               (16 x 128: dW2 in rows 0..2)
+//   P3 = dp1^T [x|1][32:48]    (128 x 16: db1 in column 7)
+//   P4 = dl^T [x|1][32:48]     (16 x 16: db2 in column 7)
+// one fused pass: each block owns a contiguous range of samples, stages 16
+// full rows at a time in LDS and runs all 105 output tiles on FP32 MFMA
+// (K = samples), writing one partial per block; k_wgrad_apply adds the
+// partials in block order (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int kWgStep = 32;   // samples staged in LDS per step
+constexpr int kWgStep = 16;
+constexpr int kWgRow = kStageStride + 4;   // padded LDS row
+constexpr int kWgTiles = 24 + 64 + 8 + 8 + 1;
+constexpr int kWgWaves = 8;
+constexpr int kWgTPW = (kWgTiles + kWgWaves - 1) / kWgWaves;
 
-template <int M, int N>
-__global__ __launch_bounds__(256) void k_wgrad(const float *stage, const uint32_t *total_p, int a_col, int b_col,
-                                               float *partials, int64_t slab)
+struct WgTile {
+    int a_col, b_col, out;   // stage columns of A and B, offset of the 16x16 tile in the partial
+    int ld;                  // row length of the partial matrix
+};
+
+__device__ __forceinline__ WgTile wg_tile(int t)
 {
-    constexpr int MT = M / 16, NTL = N / 16, TILES = MT * NTL;
-    constexpr int TPW = (TILES + 3) / 4;
-    __shared__ float As[kWgStep][M + 4];
-    __shared__ float Bs[kWgStep][N + 4];
+    constexpr int P1 = 128 * 48, P2 = P1 + 128 * 128, P3 = P2 + 16 * 128, P4 = P3 + 128 * 16;
+    if (t < 24) {
+        const int mt = t / 3, nt = t % 3;
+        return {kStDP0 + 16 * mt, kStX + 16 * nt, (16 * mt) * 48 + 16 * nt, 48};
+    }
+    t -= 24;
+    if (t < 64) {
+        const int mt = t / 8, nt = t % 8;
+        return {kStDP1 + 16 * mt, kStH1 + 16 * nt, P1 + (16 * mt) * 128 + 16 * nt, 128};
+    }
+    t -= 64;
+    if (t < 8) return {kStDL, kStH2 + 16 * t, P2 + 16 * t, 128};
+    t -= 8;
+    if (t < 8) return {kStDP1 + 16 * t, kStX + 32, P3 + (16 * t) * 16, 16};
+    return {kStDL, kStX + 32, P4, 16};
+}
+
+__global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, const uint32_t *total_p, float *partials,
+                                               int64_t slab)
+{
+    __shared__ float rows[kWgStep * kWgRow];
     const int lane = lane_id(), wave = threadIdx.x / 64;
     const int64_t total = (int64_t)*total_p;
     const int64_t s0 = (int64_t)blockIdx.x * slab;
     const int64_t s1 = (s0 + slab < total) ? s0 + slab : total;
-    f4_t acc[TPW];
+    f4_t acc[kWgTPW];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < kWgTPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+    constexpr int kF4Row = kStageStride / 4;
     for (int64_t sb = s0; sb < s1; sb += kWgStep) {
-        for (int e = threadIdx.x; e < kWgStep * M; e += 256) {
-            const int r = e / M, c = e % M;
-            As[r][c] = (sb + r < s1) ? stage[(sb + r) * kStageStride + a_col + c] : 0.f;
-        }
-        for (int e = threadIdx.x; e < kWgStep * N; e += 256) {
-            const int r = e / N, c = e % N;
-            Bs[r][c] = (sb + r < s1) ? stage[(sb + r) * kStageStride + b_col + c] : 0.f;
+        for (int e = threadIdx.x; e < kWgStep * kF4Row; e += kWgWaves * 64) {
+            const int r = e / kF4Row, c4 = e % kF4Row;
+            const f4_t v = (sb + r < s1) ? *(const f4_t *)(stage + (sb + r) * kStageStride + 4 * c4)
+                                         : f4_t{0.f, 0.f, 0.f, 0.f};
+            *(f4_t *)(rows + r * kWgRow + 4 * c4) = v;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kWgStep; kk += 4) {
+            const float *rr = rows + (kk + (lane >> 4)) * kWgRow + (lane & 15);
 #pragma unroll
-            for (int i = 0; i < TPW; ++i) {
-                const int tile = wave * TPW + i;
-                if (tile < TILES) {
-                    const int mt = tile / NTL, ntl = tile % NTL;
-                    const float a = As[kk + (lane >> 4)][16 * mt + (lane & 15)];
-                    const float bv = Bs[kk + (lane >> 4)][16 * ntl + (lane & 15)];
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
+            for (int i = 0; i < kWgTPW; ++i) {
+                const int t = wave + kWgWaves * i;
+                if (t < kWgTiles) {
+                    const WgTile w = wg_tile(t);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[w.a_col], rr[w.b_col], acc[i], 0, 0, 0);
                 }
             }
         }
         __syncthreads();
     }
-    float *out = partials + (int64_t)blockIdx.x * M * N;
+    float *out = partials + (int64_t)blockIdx.x * kPartialFloats;
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tile = wave * TPW + i;
-        if (tile < TILES) {
-            const int mt = tile / NTL, ntl = tile % NTL;
+    for (int i = 0; i < kWgTPW; ++i) {
+        const int t = wave + kWgWaves * i;
+        if (t < kWgTiles) {
+            const WgTile w = wg_tile(t);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[(16 * mt + 4 * (lane >> 4) + r) * N + 16 * ntl + (lane & 15)] = acc[i][r];
+            for (int r = 0; r < 4; ++r) out[w.out + (4 * (lane >> 4) + r) * w.ld + (lane & 15)] = acc[i][r];
         }
     }
 }
 
 // Sum the per-block partials in block order and add into the gradients.
-__global__ __launch_bounds__(256) void k_wgrad_apply(const float *partials, BackwardBufs bb)
+__global__ __launch_bounds__(256) void k_wgrad_apply(const float *partials, int nblk, BackwardBufs bb)
 {
-    const int64_t P0 = 0, P1 = P0 + (int64_t)kWgBlocks * 128 * 48, P2 = P1 + (int64_t)kWgBlocks * 128 * 128,
-                  P3 = P2 + (int64_t)kWgBlocks * 16 * 128, P4 = P3 + (int64_t)kWgBlocks * 128 * 16;
+    constexpr int P1 = 128 * 48, P2 = P1 + 128 * 128, P3 = P2 + 16 * 128, P4 = P3 + 128 * 16;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    auto sum = [&](int64_t base, int mn, int idx) {
-        float s = 0.f;
-        for (int blk = 0; blk < kWgBlocks; ++blk) s += partials[base + (int64_t)blk * mn + idx];
-        return s;
-    };
-    if (e < 128 * 39) {                       // dW0
-        const int o = e / 39, i = e % 39;
-        bb.d_w0[e] += sum(P0, 128 * 48, o * 48 + i);
-    } else if (e < 128 * 39 + 128) {          // db0 (constant-1 column)
+    int src;
+    float *dst;
+    if (e < 128 * 39) {
+        src = (e / 39) * 48 + e % 39;
+        dst = bb.d_w0 + e;
+    } else if (e < 128 * 39 + 128) {
         const int o = e - 128 * 39;
-        bb.d_b0[o] += sum(P0, 128 * 48, o * 48 + 39);
-    } else if (e < 128 * 39 + 128 + 128 * 128) {   // dW1
+        src = o * 48 + 39;
+        dst = bb.d_b0 + o;
+    } else if (e < 128 * 39 + 128 + 128 * 128) {
         const int k = e - (128 * 39 + 128);
-        bb.d_w1[k] += sum(P1, 128 * 128, k);
-    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128) {   // dW2
+        src = P1 + k;
+        dst = bb.d_w1 + k;
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128) {
         const int k = e - (128 * 39 + 128 + 128 * 128);
-        bb.d_w2[k] += sum(P2, 16 * 128, k);
-    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128) {   // db1 = dp1^T [x|1] column 39
+        src = P2 + k;
+        dst = bb.d_w2 + k;
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128) {
         const int o = e - (128 * 39 + 128 + 128 * 128 + 3 * 128);
-        bb.d_b1[o] += sum(P3, 128 * 16, o * 16 + 7);
-    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3) {   // db2
+        src = P3 + o * 16 + 7;
+        dst = bb.d_b1 + o;
+    } else if (e < 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3) {
         const int ch = e - (128 * 39 + 128 + 128 * 128 + 3 * 128 + 128);
-        bb.d_b2[ch] += sum(P4, 16 * 16, ch * 16 + 7);
+        src = P4 + ch * 16 + 7;
+        dst = bb.d_b2 + ch;
+    } else {
+        return;
     }
+    float sum = 0.f;
+    for (int blk = 0; blk < nblk; ++blk) sum += partials[(int64_t)blk * kPartialFloats + src];
+    *dst += sum;
 }
 
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
-    // slab per block from the pass's maximum sample count
+    // sample range per block from the pass's maximum sample count
     const int64_t max_s = b.n * (int64_t)b.n_samples;
     const int64_t slab = ((max_s + kWgBlocks - 1) / kWgBlocks + kWgStep - 1) / kWgStep * kWgStep;
-    const uint32_t *tot = b.offsets + b.n;
-    float *P = bb.partials;
-    const int64_t P1 = (int64_t)kWgBlocks * 128 * 48, P2 = P1 + (int64_t)kWgBlocks * 128 * 128,
-                  P3 = P2 + (int64_t)kWgBlocks * 16 * 128, P4 = P3 + (int64_t)kWgBlocks * 128 * 16;
-    const dim3 grid(kWgBlocks), blk(256);
-    hipLaunchKernelGGL((k_wgrad<128, 48>), grid, blk, 0, s, b.stage, tot, kStDP0, kStX, P, slab);
-    hipLaunchKernelGGL((k_wgrad<128, 128>), grid, blk, 0, s, b.stage, tot, kStDP1, kStH1, P + P1, slab);
-    hipLaunchKernelGGL((k_wgrad<16, 128>), grid, blk, 0, s, b.stage, tot, kStDL, kStH2, P + P2, slab);
-    hipLaunchKernelGGL((k_wgrad<128, 16>), grid, blk, 0, s, b.stage, tot, kStDP1, kStX + 32, P + P3, slab);
-    hipLaunchKernelGGL((k_wgrad<16, 16>), grid, blk, 0, s, b.stage, tot, kStDL, kStX + 32, P + P4, slab);
+    hipLaunchKernelGGL(k_wgrad, dim3(kWgBlocks), dim3(kWgWaves * 64), 0, s, (const float *)b.stage, b.offsets + b.n,
+                       bb.partials, slab);
     const int n_out = 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3;
-    hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + 255) / 256), dim3(256), 0, s, (const float *)P, bb);
+    hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + 255) / 256), dim3(256), 0, s, (const float *)bb.partials,
+                       kWgBlocks, bb);
 }
 
 }  // namespace cic

@@ -89,7 +89,7 @@ struct BackwardBufs {
     float *rec_dc;         // [n*N*3] dL/dc per live sample
     float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
 };
-constexpr int kWgBlocks = 256;
+constexpr int kWgBlocks = 1024;
 // per-block partial products: dp0^T[x|1] (128x48), dp1^T h1 (128x128),
 // dl^T h2 (16x128), dp1^T ones (128x16), dl^T ones (16x16)
 constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 * 16;
