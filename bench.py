@@ -286,6 +286,32 @@ def cpu_baseline(scene, target_s=12.0):
             "sample": "%d seeded pixels of the 800x800 frame (%d evaluated samples, %.1f s)" % (n, ns, dt)}
 
 
+def profile_run():
+    """Short fixed workload for hardware-counter passes: a 1 GiB device copy
+    (calibrates FETCH_SIZE / WRITE_SIZE against known bytes), then two 800x800
+    frames in ray order, two in voxel order, one 8-view BF16 launch and one
+    training step."""
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    model, scene = build_scene(160, "cuda:0")
+    cam = camera(800, 800, synth.orbit_pose(0))
+    for order in (cic.CIC_ORDER_RAY, cic.CIC_ORDER_VOXEL):
+        opts = cic.make_opts(256, 1e-4, True, order=order)
+        for _ in range(2):
+            cic.render_frame(model, opts, cam)
+    torch.cuda.synchronize()
+    precision_bench(scene, model.occupancy, 1)
+    fwd_bwd_bench(1)
+    torch.cuda.synchronize()
+    print("profile run done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +322,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--skip-fwd-bwd", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="run the short fixed workload used for rocprofv3 counter passes and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -303,6 +331,9 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.profile_run:
+        profile_run()
+        return
     import torch
     import paper_2404_11852_amd as cic
     device = "cuda:0"
