@@ -224,7 +224,8 @@ enum {
     CIC_STAGE_BACKWARD = 6,   /* adjoint: compositing adjoint + density scatter */
     CIC_STAGE_BWD_MLP = 7,    /* adjoint: MLP backward + feature scatter */
     CIC_STAGE_BWD_WGRAD = 8,  /* adjoint: weight-gradient products */
-    CIC_STAGE_COUNT = 9
+    CIC_STAGE_EMBED = 9,      /* per-ray direction term of layer 0 */
+    CIC_STAGE_COUNT = 10
 };
 int cic_timing_enable(int on);
 int cic_timing_read(double *ms, int64_t *launches, int n_stages);

@@ -51,7 +51,7 @@ class Camera(C.Structure):
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
            "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
            "cic_timing_read"]
-STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad"]
+STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad", "embed"]
 
 _lib = None
 _lock = threading.Lock()

@@ -167,6 +167,7 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
     b.rec_k = cv.take<uint16_t>(ns);
     b.rec_w = cv.take<float>(ns);
     b.rec_c = cv.take<float>(3 * ns);
+    if (!voxel) b.z0 = cv.take<float>(128 * nc);
     if (voxel) {
         b.rec_key = cv.take<uint32_t>(ns);
         b.brick_off = cv.take<uint32_t>(n_bricks + 1);
@@ -352,6 +353,10 @@ void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, con
             launch_exclusive_scan(b.brick_off, b.brick_off, b.brick_tmp, b.n_bricks, s);
             launch_brick_scatter(b, s);
         }
+    }
+    if (!voxel && mlp->compute == CIC_F32) {
+        StageTimer t(CIC_STAGE_EMBED, s);
+        launch_ray_embed(*mlp, b, s);
     }
     {
         StageTimer t(CIC_STAGE_MLP, s);

@@ -16,7 +16,10 @@ namespace cic {
 constexpr int kWave = 64;
 constexpr int kBrick = 8;            // voxels per brick edge (voxel-order bucketing)
 constexpr int kMaxSamples = 1024;    // samples per ray
-constexpr int64_t kChunkRays = 1 << 21;  // rays per pipeline pass
+#ifndef CIC_CHUNK_LOG2
+#define CIC_CHUNK_LOG2 21
+#endif
+constexpr int64_t kChunkRays = (int64_t)1 << CIC_CHUNK_LOG2;  // rays per pipeline pass
 
 // Grid description as the kernels see it (filled on the host).
 struct GridK {

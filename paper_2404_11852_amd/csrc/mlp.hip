@@ -86,8 +86,10 @@ __device__ void stage_weights_f32(const cic_mlp &m, float *lds)
 
 __device__ __forceinline__ float pick3(int i, float a, float b, float c) { return i == 0 ? a : (i == 1 ? b : c); }
 
-// Layer-0 inputs of one sample for this lane's group q.
-template <typename T>
+// Layer-0 inputs of one sample for this lane's group q (PE = false: only
+// the three feature channels; the direction terms come from the per-ray
+// table).
+template <typename T, bool PE = true>
 __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &b, int64_t rec, int q, float x[10])
 {
     const uint32_t ray = b.rec_ray[rec];
@@ -105,6 +107,11 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
     const T *feat = (const T *)g.features;
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+    if (!PE) {
+#pragma unroll
+        for (int c = 3; c < 10; ++c) x[c] = 0.f;
+        return;
+    }
     x[3] = q < 3 ? pick3(q, d[0], d[1], d[2]) : 0.f;
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
@@ -117,9 +124,77 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
     }
 }
 
+// Batch range of this workgroup's XCD.  Workgroups are dispatched to the 8
+// XCDs round-robin, so blocks x, x+8, x+16, ... share one L2; giving each
+// XCD one contiguous eighth of the (ray-ordered) samples keeps the grid
+// region those rays touch in that XCD's L2.  (Only performance depends on
+// the dispatch order.)
+constexpr int kXcds = 8;
+struct BatchRange {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ BatchRange xcd_batches(int64_t nbatch, int waves, int wave)
+{
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
+    const int64_t per = (nbatch + kXcds - 1) / kXcds;
+    const int64_t lo = xcd * per, hi = lo + per < nbatch ? lo + per : nbatch;
+    return {lo + (int64_t)slot * waves + wave, hi, (int64_t)nslots * waves};
+}
+
+// Per-ray direction term of layer 0: z0[ray][o] = b0[o] + sum_i W0[o][12+i] pe_i
+// over the 27 direction inputs (d, sin, cos), once per ray with live samples
+// (float32; used by the FP32 MLP in ray order).
+constexpr int kEmbedRays = 16;
+
+__global__ __launch_bounds__(128) void k_ray_embed(cic_mlp m, RenderBufs b, float *z0)
+{
+    __shared__ float pe[kEmbedRays][28];
+    const int o = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kEmbedRays;
+    for (int e = threadIdx.x; e < kEmbedRays * 27; e += 128) {
+        const int r = e / 27, i = e % 27;
+        const int64_t ray = base + r;
+        float v = 0.f;
+        if (ray < b.n && b.count[ray] != 0) {
+            const float *d = b.rays_d + 3 * ray;
+            if (i < 3) {
+                v = d[i];
+            } else {
+                const int k = (i - 3) % 12, c = k >> 2, oc = k & 3;
+                float sn, cs;
+                sincosf(ldexpf(d[c], oc), &sn, &cs);
+                v = i < 15 ? sn : cs;
+            }
+        }
+        pe[r][i] = v;
+    }
+    __syncthreads();
+    float w[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) w[i] = m.w0[o * 39 + 12 + i];
+    const float bias = m.b0[o];
+    for (int r = 0; r < kEmbedRays; ++r) {
+        const int64_t ray = base + r;
+        if (ray >= b.n || b.count[ray] == 0) continue;
+        float acc = bias;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) acc = fmaf(w[i], pe[r][i], acc);
+        z0[ray * 128 + o] = acc;
+    }
+}
+
+void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s)
+{
+    if (b.n == 0 || m.compute != CIC_F32) return;
+    const unsigned blocks = (unsigned)((b.n + kEmbedRays - 1) / kEmbedRays);
+    hipLaunchKernelGGL(k_ray_embed, dim3(blocks), dim3(128), 0, s, m, b, b.z0);
+}
+
 // STAGE: also write x (with the constant-1 slot), h1 and h2 of every sample
-// to its stage row for the adjoint's weight gradients.
-template <typename T, bool STAGE>
+// to its stage row for the adjoint's weight gradients.  PET: the direction
+// half of layer 0 comes from the per-ray table (ray order), so layer 0 only
+// multiplies the 12 interpolated features.
+template <typename T, bool STAGE, bool PET>
 __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
     extern __shared__ float lds[];
@@ -134,7 +209,8 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
     const f4_t *w1f = (const f4_t *)(lds + kOffW1);
     const f4_t *w2l = (const f4_t *)(lds + kOffW2);
 
-    for (int64_t bt = (int64_t)blockIdx.x * kMlpWaves + wave; bt < nbatch; bt += (int64_t)gridDim.x * kMlpWaves) {
+    const BatchRange br = xcd_batches(nbatch, kMlpWaves, wave);
+    for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
         float x[kNT][10];
         int64_t rec[kNT];
         bool valid[kNT];
@@ -144,7 +220,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             valid[nt] = s < total;
             rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             if (valid[nt]) {
-                sample_inputs<T>(g, b, rec[nt], q, x[nt]);
+                sample_inputs<T, !PET>(g, b, rec[nt], q, x[nt]);
                 if (STAGE) {
                     float *row = b.stage + rec[nt] * kStageStride + kStX;
 #pragma unroll
@@ -159,32 +235,45 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             }
         }
 
-        // layer 0: 40 -> 128
+        // layer 0: 40 -> 128 (PET: 12 -> 128 on top of the per-ray term)
         f4_t h1[8][kNT];
+        if (PET) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const f4_t bias = *(const f4_t *)(lds + kOffB0 + 16 * t + 4 * q);
+            for (int nt = 0; nt < kNT; ++nt) {
+                const float *zr = b.z0 + (int64_t)b.rec_ray[rec[nt]] * 128 + 4 * q;
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) h1[t][nt] = bias;
+                for (int t = 0; t < 8; ++t)
+                    h1[t][nt] = valid[nt] ? *(const f4_t *)(zr + 16 * t) : f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const f4_t bias = *(const f4_t *)(lds + kOffB0 + 16 * t + 4 * q);
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt) h1[t][nt] = bias;
+            }
         }
         // Layer 0: per input chunk pair, the eight output tiles' A fragments
         // are read together and the MFMAs alternate between the eight
         // independent accumulators.  The scheduling barriers keep the
         // compiler from hoisting every LDS read (which would exceed the
         // register budget).
+        constexpr int kC2 = PET ? 2 : 5;   // PET: chunks 0..2 (features) only
 #pragma unroll
-        for (int c2 = 0; c2 < 5; ++c2) {
+        for (int c2 = 0; c2 < kC2; ++c2) {
             f2_t a[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) a[t] = w0f[(t * 5 + c2) * 64 + lane];
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
+            for (int e = 0; e < 2; ++e) {
+                if (PET && 2 * c2 + e >= 3) continue;
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
 #pragma unroll
                     for (int nt = 0; nt < kNT; ++nt)
                         h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][e], x[nt][2 * c2 + e], h1[t][nt], 0, 0,
                                                                           0);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
@@ -382,8 +471,9 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
     const int wave = threadIdx.x / 64;
     const int64_t total = (int64_t)b.offsets[b.n];
     const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
+    const BatchRange br = xcd_batches(nbatch, kBfWaves, wave);
 
-    for (int64_t bt = (int64_t)blockIdx.x * kBfWaves + wave; bt < nbatch; bt += (int64_t)gridDim.x * kBfWaves) {
+    for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
         bf8_t xin[kBfNT][2];
         int64_t rec[kBfNT];
         bool valid[kBfNT];
@@ -404,6 +494,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
                 xin[nt][0][e] = (__bf16)x[e];
                 xin[nt][1][e] = (__bf16)(e < 2 ? x[8 + e] : 0.f);
             }
+
         }
         // layer 0
         f4_t h1[8][kBfNT];
@@ -495,41 +586,53 @@ static int num_cus()
     return n > 0 ? n : 256;
 }
 
-template <typename T, bool STAGE>
+template <typename T, bool STAGE, bool PET>
 static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
     const int lds = mlp_lds_bytes(m.compute);
     static bool attr_set = false;   // per process; the attribute is per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T, STAGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  lds);
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T, STAGE, PET>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE>), dim3(num_cus()), dim3(kMlpWaves * 64), lds, s, g, m, b,
+    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE, PET>), dim3(num_cus()), dim3(kMlpWaves * 64), lds, s, g, m, b,
                        voxel ? 1 : 0);
 }
 
 template <typename T>
+static void launch_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kLdsBf16);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus() * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
+                       voxel ? 1 : 0);
+}
+
+// FP32 in ray order uses the per-ray direction table (b.z0 must be filled
+// by launch_ray_embed first); voxel order and the BF16 kernel evaluate the
+// encoding per sample (measured: in the vector-ALU-bound BF16 kernel the
+// table's extra loads cost more than the per-sample encoding they replace).
+template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
     if (m.compute == CIC_BF16) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      kLdsBf16);
-            attr_set = true;
-        }
-        hipLaunchKernelGGL(k_mlp_fwd_bf16<T>, dim3(num_cus() * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
-                           voxel ? 1 : 0);
+        launch_bf16<T>(g, m, b, voxel, s);
         return;
     }
-    launch_fwd<T, false>(g, m, b, voxel, s);
+    if (voxel) launch_fwd<T, false, false>(g, m, b, true, s);
+    else launch_fwd<T, false, true>(g, m, b, false, s);
 }
 
 void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s)
 {
-    launch_fwd<float, true>(g, m, b, false, s);
+    launch_fwd<float, true, false>(g, m, b, false, s);
 }
+
 template void launch_mlp_forward<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
 template void launch_mlp_forward<__half>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
 
