@@ -78,16 +78,20 @@ def timed_frames(model, opts, cam, steps, warmup):
     return t1 - t0, int(n_eval.item()), stages
 
 
-def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16):
-    """32-frame orbit, references every 16th frame rendered in full, targets
-    warped from the nearest reference (ties to the earlier one) with holes
-    re-rendered.  Returns timing and quality against full renders."""
+def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0, full=None):
+    """Orbit of n_frames, references every ref_every-th frame rendered in
+    full, targets warped from the nearest reference (ties to the earlier one)
+    with holes re-rendered; max_angle_deg > 0 turns on the warp-angle test.
+    Returns timing and quality against full renders (passed in as `full`, or
+    rendered here)."""
     import torch
     import synth
     import paper_2404_11852_amd as cic
     poses = [synth.orbit_pose(k) for k in range(n_frames)]
     refs = list(range(0, n_frames, ref_every))
     cams = [camera(W, H, p) for p in poses]
+    sopts = cic.make_opts(opts.n_samples, opts.et_threshold, bool(opts.use_occupancy), tuple(opts.bg),
+                          opts.void_acc, opts.order, warp_max_angle=max_angle_deg)
 
     def nearest(k):
         return min(refs, key=lambda r: (abs(k - r), r))
@@ -106,7 +110,7 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16):
                 continue
             r = nearest(k)
             T = synth.relative_pose(synth.as_f32(poses[r]), synth.as_f32(poses[k]))
-            rgb, dz, mask, n_masked = cic.render_frame_sparw(model, opts, cams[r], ref_img[r][0], ref_img[r][1],
+            rgb, dz, mask, n_masked = cic.render_frame_sparw(model, sopts, cams[r], ref_img[r][0], ref_img[r][1],
                                                              cams[k], torch.from_numpy(T))
             out[k] = rgb
             nm.append(n_masked)
@@ -127,25 +131,47 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16):
             continue
         r = nearest(k)
         T = synth.relative_pose(synth.as_f32(poses[r]), synth.as_f32(poses[k]))
-        cic.render_frame_sparw(model, opts, cams[r], ref_rgbd[r][0], ref_rgbd[r][1], cams[k], torch.from_numpy(T))
+        cic.render_frame_sparw(model, sopts, cams[r], ref_rgbd[r][0], ref_rgbd[r][1], cams[k], torch.from_numpy(T))
     torch.cuda.synchronize()
     tt1 = time.perf_counter()
-    full_t0 = time.perf_counter()
-    full = [cic.render_frame(model, opts, c)[0] for c in cams]
-    torch.cuda.synchronize()
-    full_t1 = time.perf_counter()
+    full_s = None
+    if full is None:
+        full_t0 = time.perf_counter()
+        full = [cic.render_frame(model, opts, c)[0] for c in cams]
+        torch.cuda.synchronize()
+        full_s = time.perf_counter() - full_t0
     ps = [psnr(out[k], full[k]) for k in range(n_frames) if k not in refs]
     fr = [int(x.item()) / float(W * H) for x in nm]
     n_t = n_frames - len(refs)
-    return {
-        "frames": n_frames, "references": len(refs), "window": ref_every,
+    res = {
+        "frames": n_frames, "references": len(refs), "window": ref_every, "max_angle_deg": max_angle_deg,
         "fps": n_frames / (t1 - t0),
-        "fps_full_render": n_frames / (full_t1 - full_t0),
-        "speedup_vs_full": (full_t1 - full_t0) / (t1 - t0),
         "ms_per_target": 1e3 * (tt1 - tt0) / n_t,
         "mask_fraction_mean": sum(fr) / len(fr), "mask_fraction_max": max(fr),
         "psnr_vs_full_mean_db": sum(ps) / len(ps), "psnr_vs_full_min_db": min(ps),
     }
+    if full_s is not None:
+        res["fps_full_render"] = n_frames / full_s
+        res["speedup_vs_full"] = full_s / (t1 - t0)
+    return res, full
+
+
+def sparw_sweep(model, opts, W, H, windows=(6, 16, 26), angles=(0.0, 8.0, 4.0, 2.0), n_frames=32):
+    """Window / warp-angle sweep over one orbit (Sec. III-C): the first entry
+    (window 16, no angle test) also carries the full-render comparison."""
+    base, full = sparw_orbit(model, opts, W, H, n_frames=n_frames, ref_every=16)
+    sweep = []
+    for w in windows:
+        for a in angles:
+            if w == 16 and a == 0.0:
+                r = dict(base)
+            else:
+                r, _ = sparw_orbit(model, opts, W, H, n_frames=n_frames, ref_every=w, max_angle_deg=a, full=full)
+            r["speedup_vs_full"] = base["fps_full_render"] and r["fps"] / base["fps_full_render"]
+            sweep.append({k: r[k] for k in ("window", "max_angle_deg", "fps", "ms_per_target", "mask_fraction_mean",
+                                            "psnr_vs_full_mean_db", "psnr_vs_full_min_db", "speedup_vs_full")})
+    base["sweep"] = sweep
+    return base
 
 
 def precision_bench(scene, occ, steps):
@@ -391,7 +417,7 @@ def main():
     }
     if not args.skip_sparw:
         log("SpaRW orbit")
-        out["sparw"] = sparw_orbit(model, opts, W, H)
+        out["sparw"] = sparw_sweep(model, opts, W, H)
     if not args.skip_precision:
         log("precision path (8 views, FP16 grid + BF16 MLP)")
         out["precision"] = precision_bench(scene, model.occupancy, max(3, args.steps // 4))

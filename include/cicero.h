@@ -102,6 +102,9 @@ typedef struct {
     float bg[3];               /* background colour added with weight T_stop */
     float void_acc;            /* frames: z-depth is +inf where opacity < void_acc */
     int32_t order;             /* CIC_ORDER_RAY or CIC_ORDER_VOXEL */
+    float warp_max_angle;      /* SpaRW: degrees; a target pixel is warped only if the rays from the two
+                                  cameras to its visible reference point subtend less than this, else
+                                  rendered (Sec. III-C); 0 = off */
 } cic_opts;
 
 typedef struct {
@@ -172,12 +175,18 @@ int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
  * image.  A reference pixel with depth +inf is a direction: it is rotated
  * only and carries depth +inf.  Each target pixel keeps the smallest depth,
  * ties to the smallest reference pixel index (64-bit packed-key atomic min).
+ * max_angle_deg > 0 adds the "when to warp" test of Sec. III-C to the
+ * visible (z-buffer winning) point of each target pixel: a finite point whose
+ * rays from the two camera centres subtend max_angle_deg or more
+ * (cos <= cos(max_angle), float32; the reference centre in target coordinates
+ * is the translation of ref_T_tgt) leaves the pixel a hole, to be rendered;
+ * points at infinity always pass.
  * Outputs (target size): tgt_rgb [H][W][3], tgt_depth_z [H][W] (+inf for
  * directions, 0 where nothing landed), mask [H][W] u8 (1 = nothing landed,
  * the disoccluded pixels to re-render), src_index [H][W] int32 (nullable;
  * reference pixel or -1).  Reference rgb/depth: [Hr][Wr][3], [Hr][Wr]. */
 int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12],
-               const float *ref_rgb, const float *ref_depth_z,
+               const float *ref_rgb, const float *ref_depth_z, float max_angle_deg,
                float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
                void *ws, size_t ws_bytes, cic_stream_t stream);
 

@@ -44,7 +44,8 @@ class MLP(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("et_threshold", C.c_float),
-                ("use_occupancy", C.c_int32), ("bg", C.c_float * 3), ("void_acc", C.c_float)]
+                ("use_occupancy", C.c_int32), ("bg", C.c_float * 3), ("void_acc", C.c_float),
+                ("warp_max_angle", C.c_float)]
 
 
 class Cam(C.Structure):
@@ -98,9 +99,10 @@ class Model:
         self.grid.occ = None if self.occ is None else _p(self.occ).value
 
 
-def opts(n_samples, et_threshold=0.0, use_occupancy=False, bg=(1.0, 1.0, 1.0), void_acc=1e-4):
+def opts(n_samples, et_threshold=0.0, use_occupancy=False, bg=(1.0, 1.0, 1.0), void_acc=1e-4,
+         warp_max_angle=0.0):
     return Opts(int(n_samples), float(et_threshold), int(bool(use_occupancy)),
-                (C.c_float * 3)(*bg), float(void_acc))
+                (C.c_float * 3)(*bg), float(void_acc), float(warp_max_angle))
 
 
 def camera(width, height, f, cx, cy, c2w):
@@ -210,7 +212,7 @@ def render_pixels(model, op, cam, pix=None):
     return rgb, dz, acc, {"n_eval": ne, "margin": mg, "acc_margin": am}
 
 
-def warp(ref_cam, tgt_cam, T, ref_rgb, ref_depth):
+def warp(ref_cam, tgt_cam, T, ref_rgb, ref_depth, max_angle_deg=0.0):
     ref_rgb = _f32(ref_rgb).reshape(-1, 3)
     ref_depth = _f32(ref_depth).reshape(-1)
     T = _f32(T).reshape(12)
@@ -219,8 +221,8 @@ def warp(ref_cam, tgt_cam, T, ref_rgb, ref_depth):
     dep = np.empty(n, np.float32)
     mask = np.empty(n, np.uint8)
     src = np.empty(n, np.int32)
-    lib().orc_warp(C.byref(ref_cam), C.byref(tgt_cam), _p(T), _p(ref_rgb), _p(ref_depth),
-                   _p(rgb), _p(dep), _p(mask), _p(src))
+    lib().orc_warp_angle(C.byref(ref_cam), C.byref(tgt_cam), _p(T), _p(ref_rgb), _p(ref_depth),
+                         C.c_float(max_angle_deg), _p(rgb), _p(dep), _p(mask), _p(src))
     return rgb, dep, mask, src
 
 

@@ -76,6 +76,7 @@ typedef struct {
     int32_t use_occupancy;
     float bg[3];
     float void_acc;          /* frame depth is +inf when acc < this */
+    float warp_max_angle;    /* degrees; 0 = no angle test in the warp */
 } orc_opts;
 
 typedef struct {
@@ -546,10 +547,61 @@ static float bits_f32(uint32_t u)
  * Outputs (target size): rgb [H][W][3], depth [H][W] (target z, +inf for
  * directions, 0 for holes), mask [H][W] (1 = no splat landed), src [H][W]
  * (reference pixel index or -1; may be NULL). */
-void orc_warp(const orc_camera *ref, const orc_camera *tgt, const float T[12],
-              const float *ref_rgb, const float *ref_depth,
-              float *tgt_rgb, float *tgt_depth, uint8_t *mask, int32_t *src_out)
+/* Warping is allowed only where the angle, at the scene point, between the
+ * reference camera's ray and the target camera's ray is below a threshold
+ * (Sec. III-C, "Deciding When to Warp").  In target-camera coordinates the
+ * target centre is the origin and the reference centre is t = (T[3], T[7],
+ * T[11]); the test is cos(angle) > cos(max_angle), in float32.  Points at
+ * infinity subtend no angle.  max_angle_deg <= 0 disables the test. */
+static float cos_limit(float max_angle_deg)
 {
+    return max_angle_deg > 0.0f ? (float)cos((double)max_angle_deg * 3.14159265358979323846 / 180.0) : -2.0f;
+}
+
+static int angle_ok(const float T[12], float Xt, float Yt, float Zt, float cmin)
+{
+    if (cmin < -1.0f) return 1;
+    float rx = Xt - T[3], ry = Yt - T[7], rz = Zt - T[11];
+    float dot = (Xt * rx + Yt * ry) + Zt * rz;
+    float n1 = sqrtf((Xt * Xt + Yt * Yt) + Zt * Zt);
+    float n2 = sqrtf((rx * rx + ry * ry) + rz * rz);
+    return dot / (n1 * n2) > cmin;
+}
+
+/* Steps 1-2 for one reference pixel: back-project along its ray to depth D
+ * (Eq. 1) and move the point into target-camera coordinates (Eq. 2).  A
+ * point at infinity moves by the rotation only (a direction); its z-buffer
+ * depth is +inf.  Float32, expression order as written. */
+static void warp_point(const orc_camera *ref, const float T[12], int i, int j, float D,
+                       float *Xt, float *Yt, float *Zt, float *kz)
+{
+    float a = (((float)i + 0.5f) - ref->cx) / ref->f;
+    float b = (((float)j + 0.5f) - ref->cy) / ref->f;
+    if (D == INFINITY) {
+        *Xt = (T[0] * a + T[1] * b) + T[2];
+        *Yt = (T[4] * a + T[5] * b) + T[6];
+        *Zt = (T[8] * a + T[9] * b) + T[10];
+        *kz = INFINITY;
+    } else {
+        float X = D * a, Y = D * b, Z = D;
+        *Xt = ((T[0] * X + T[1] * Y) + T[2] * Z) + T[3];
+        *Yt = ((T[4] * X + T[5] * Y) + T[6] * Z) + T[7];
+        *Zt = ((T[8] * X + T[9] * Y) + T[10] * Z) + T[11];
+        *kz = *Zt;
+    }
+}
+
+/* Steps 1-3 of Sec. III-B with the when-to-warp test of Sec. III-C.  The
+ * z-buffer decides which reference point is visible at each target pixel
+ * (nearest depth, ties to the smaller reference index); the angle test is
+ * then applied to that visible point, and a pixel whose point fails it is
+ * left for rendering like a disocclusion hole (a failing point does not
+ * uncover what lies behind it).  max_angle_deg <= 0 disables the test. */
+void orc_warp_angle(const orc_camera *ref, const orc_camera *tgt, const float T[12],
+                    const float *ref_rgb, const float *ref_depth, float max_angle_deg,
+                    float *tgt_rgb, float *tgt_depth, uint8_t *mask, int32_t *src_out)
+{
+    const float cmin = cos_limit(max_angle_deg);
     int W = ref->width, H = ref->height, Wt = tgt->width, Ht = tgt->height;
     int64_t np = (int64_t)Wt * Ht;
     uint64_t *zbuf = (uint64_t *)malloc(sizeof(uint64_t) * np);
@@ -559,21 +611,8 @@ void orc_warp(const orc_camera *ref, const orc_camera *tgt, const float T[12],
             int64_t src = (int64_t)j * W + i;
             float D = ref_depth[src];
             if (D != D) continue;
-            float a = (((float)i + 0.5f) - ref->cx) / ref->f;
-            float b = (((float)j + 0.5f) - ref->cy) / ref->f;
             float Xt, Yt, Zt, kz;
-            if (D == INFINITY) {
-                Xt = (T[0] * a + T[1] * b) + T[2];
-                Yt = (T[4] * a + T[5] * b) + T[6];
-                Zt = (T[8] * a + T[9] * b) + T[10];
-                kz = INFINITY;
-            } else {
-                float X = D * a, Y = D * b, Z = D;
-                Xt = ((T[0] * X + T[1] * Y) + T[2] * Z) + T[3];
-                Yt = ((T[4] * X + T[5] * Y) + T[6] * Z) + T[7];
-                Zt = ((T[8] * X + T[9] * Y) + T[10] * Z) + T[11];
-                kz = Zt;
-            }
+            warp_point(ref, T, i, j, D, &Xt, &Yt, &Zt, &kz);
             if (!(Zt > 0.0f)) continue;
             float u = tgt->f * (Xt / Zt) + tgt->cx;
             float v = tgt->f * (Yt / Zt) + tgt->cy;
@@ -584,7 +623,17 @@ void orc_warp(const orc_camera *ref, const orc_camera *tgt, const float T[12],
         }
     for (int64_t p = 0; p < np; ++p) {
         uint64_t key = zbuf[p];
-        if (key == UINT64_MAX) {
+        int hole = key == UINT64_MAX;
+        if (!hole && cmin >= -1.0f) {
+            uint32_t s = (uint32_t)(key & 0xffffffffu);
+            float D = ref_depth[s];
+            if (D != INFINITY) {
+                float Xt, Yt, Zt, kz;
+                warp_point(ref, T, (int)(s % (uint32_t)W), (int)(s / (uint32_t)W), D, &Xt, &Yt, &Zt, &kz);
+                hole = !angle_ok(T, Xt, Yt, Zt, cmin);
+            }
+        }
+        if (hole) {
             mask[p] = 1;
             tgt_rgb[3 * p] = tgt_rgb[3 * p + 1] = tgt_rgb[3 * p + 2] = 0.0f;
             tgt_depth[p] = 0.0f;
@@ -600,6 +649,13 @@ void orc_warp(const orc_camera *ref, const orc_camera *tgt, const float T[12],
     free(zbuf);
 }
 
+void orc_warp(const orc_camera *ref, const orc_camera *tgt, const float T[12],
+              const float *ref_rgb, const float *ref_depth,
+              float *tgt_rgb, float *tgt_depth, uint8_t *mask, int32_t *src_out)
+{
+    orc_warp_angle(ref, tgt, T, ref_rgb, ref_depth, 0.0f, tgt_rgb, tgt_depth, mask, src_out);
+}
+
 /* Eq. 4: warp, then render the hole pixels with the full model and put them
  * in place.  rgb/depth outputs are float64; mask as in orc_warp.
  * n_masked receives the hole count. */
@@ -611,7 +667,7 @@ void orc_sparw(const orc_grid *g, const orc_mlp *m, const orc_opts *op,
     int64_t np = (int64_t)tgt->width * tgt->height;
     float *wr = (float *)malloc(sizeof(float) * 3 * np);
     float *wd = (float *)malloc(sizeof(float) * np);
-    orc_warp(ref, tgt, T, ref_rgb, ref_depth, wr, wd, mask, NULL);
+    orc_warp_angle(ref, tgt, T, ref_rgb, ref_depth, op->warp_max_angle, wr, wd, mask, NULL);
     int64_t nh = 0;
     for (int64_t p = 0; p < np; ++p) nh += mask[p];
     int64_t *holes = (int64_t *)malloc(sizeof(int64_t) * (nh > 0 ? nh : 1));

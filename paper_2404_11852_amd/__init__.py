@@ -78,13 +78,14 @@ def render_frame(model, opts, cam, n_eval=None):
     return rgb, dz, acc
 
 
-def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, with_src=False):
+def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, with_src=False, max_angle_deg=0.0):
     n = tgt_cam.width * tgt_cam.height
     dev = ref_rgb.device
     rgb, dz = _f32(n, 3, device=dev), _f32(n, device=dev)
     mask = torch.empty(n, dtype=torch.uint8, device=dev)
     src = torch.empty(n, dtype=torch.int32, device=dev) if with_src else None
-    _lib.warp_frame(ref_cam, tgt_cam, T, ref_rgb.contiguous(), ref_depth.contiguous(), rgb, dz, mask, src)
+    _lib.warp_frame(ref_cam, tgt_cam, T, ref_rgb.contiguous(), ref_depth.contiguous(), rgb, dz, mask, src,
+                    max_angle_deg)
     return (rgb, dz, mask, src) if with_src else (rgb, dz, mask)
 
 

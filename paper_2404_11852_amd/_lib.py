@@ -40,7 +40,8 @@ class MLP(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("et_threshold", C.c_float), ("use_occupancy", C.c_int32),
-                ("bg", C.c_float * 3), ("void_acc", C.c_float), ("order", C.c_int32)]
+                ("bg", C.c_float * 3), ("void_acc", C.c_float), ("order", C.c_int32),
+                ("warp_max_angle", C.c_float)]
 
 
 class Camera(C.Structure):
@@ -75,7 +76,7 @@ def lib():
                 L.generate_rays.argtypes = [vp, i64, vp, vp, vp, vp]
                 L.render_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, u64, vp]
                 L.render_frame.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
-                L.warp_frame.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
+                L.warp_frame.argtypes = [vp, vp, vp, vp, vp, f, vp, vp, vp, vp, vp, u64, vp]
                 L.render_frame_sparw.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp]
                 L.render_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                               vp, vp, u64, vp]
@@ -156,9 +157,9 @@ def make_mlp(w, compute=CIC_F32):
 
 
 def make_opts(n_samples, et_threshold=0.0, use_occupancy=False, bg=(1.0, 1.0, 1.0), void_acc=1e-4,
-              order=CIC_ORDER_RAY):
+              order=CIC_ORDER_RAY, warp_max_angle=0.0):
     return Opts(int(n_samples), float(et_threshold), int(bool(use_occupancy)), (C.c_float * 3)(*bg),
-                float(void_acc), int(order))
+                float(void_acc), int(order), float(warp_max_angle))
 
 
 def make_camera(width, height, f, cx, cy, c2w):
@@ -200,13 +201,14 @@ def render_frame(grid, mlp, opts, cam, rgb, depth_z, acc=None, n_eval=None):
                               _stream()))
 
 
-def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask, src_index=None):
+def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask, src_index=None,
+               max_angle_deg=0.0):
     nb = workspace_bytes(OP_WARP_FRAME, tgt_cam.width * tgt_cam.height)
     ws = workspace(nb, ref_rgb.device)
     Tc = (C.c_float * 12)(*[float(v) for v in torch.as_tensor(T, dtype=torch.float32).reshape(12).tolist()])
     _check(lib().warp_frame(C.byref(ref_cam), C.byref(tgt_cam), Tc, _ptr(ref_rgb), _ptr(ref_depth),
-                            _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(src_index), _ptr(ws),
-                            C.c_size_t(ws.numel()), _stream()))
+                            C.c_float(max_angle_deg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(src_index),
+                            _ptr(ws), C.c_size_t(ws.numel()), _stream()))
 
 
 def render_frame_sparw(grid, mlp, opts, ref_cam, ref_rgb, ref_depth, tgt_cam, T, out_rgb, out_depth, mask,

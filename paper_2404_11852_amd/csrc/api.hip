@@ -51,6 +51,12 @@ struct Carver {
 
 bool finite_f(float v) { return std::isfinite(v); }
 
+// cos of the warp-angle limit, float32 from a float64 evaluation; < -1 = off.
+float cos_limit(float max_angle_deg)
+{
+    return max_angle_deg > 0.0f ? (float)std::cos((double)max_angle_deg * 3.14159265358979323846 / 180.0) : -2.0f;
+}
+
 int check_grid(const cic_grid *g)
 {
     if (!g) return fail(CIC_ERR_INVALID, "grid is NULL");
@@ -93,6 +99,8 @@ int check_opts(const cic_opts *o, const cic_grid *g)
     for (int c = 0; c < 3; ++c)
         if (!finite_f(o->bg[c])) return fail(CIC_ERR_INVALID, "opts.bg is not finite");
     if (!finite_f(o->void_acc) || o->void_acc < 0.f) return fail(CIC_ERR_INVALID, "opts.void_acc must be >= 0");
+    if (!finite_f(o->warp_max_angle) || o->warp_max_angle < 0.f || o->warp_max_angle > 180.f)
+        return fail(CIC_ERR_INVALID, "opts.warp_max_angle must be in [0, 180] degrees");
     return CIC_OK;
 }
 
@@ -477,11 +485,13 @@ int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
 }
 
 int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12], const float *ref_rgb,
-               const float *ref_depth_z, float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
-               void *ws, size_t ws_bytes, cic_stream_t stream)
+               const float *ref_depth_z, float max_angle_deg, float *tgt_rgb, float *tgt_depth_z, uint8_t *mask,
+               int32_t *src_index, void *ws, size_t ws_bytes, cic_stream_t stream)
 {
     int rc;
     if ((rc = check_camera(ref, "reference")) || (rc = check_camera(tgt, "target"))) return rc;
+    if (!finite_f(max_angle_deg) || max_angle_deg < 0.f || max_angle_deg > 180.f)
+        return fail(CIC_ERR_INVALID, "max_angle_deg must be in [0, 180]");
     if (!ref_T_tgt) return fail(CIC_ERR_INVALID, "ref_T_tgt is NULL");
     for (int i = 0; i < 12; ++i)
         if (!finite_f(ref_T_tgt[i])) return fail(CIC_ERR_INVALID, "ref_T_tgt is not finite");
@@ -498,8 +508,8 @@ int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_t
     WarpBufs w = carve_warp(cv, np, false);
     {
         StageTimer t(CIC_STAGE_WARP, (hipStream_t)stream);
-        launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, tgt_rgb, tgt_depth_z, mask, src_index,
-                    nullptr, nullptr, (hipStream_t)stream);
+        launch_warp(*ref, *tgt, ref_T_tgt, cos_limit(max_angle_deg), ref_rgb, ref_depth_z, w.zbuf, tgt_rgb,
+                    tgt_depth_z, mask, src_index, nullptr, nullptr, (hipStream_t)stream);
     }
     return after_launch("warp_frame");
 }
@@ -534,8 +544,8 @@ int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts 
     b.n_active = w.n_holes;
     {
         StageTimer t(CIC_STAGE_WARP, s);
-        launch_warp(*ref, *tgt, ref_T_tgt, ref_rgb, ref_depth_z, w.zbuf, out_rgb, out_depth_z, mask, nullptr,
-                    w.hole_idx, w.n_holes, s);
+        launch_warp(*ref, *tgt, ref_T_tgt, cos_limit(opts->warp_max_angle), ref_rgb, ref_depth_z, w.zbuf, out_rgb,
+                    out_depth_z, mask, nullptr, w.hole_idx, w.n_holes, s);
     }
     {
         StageTimer t(CIC_STAGE_RAYGEN, s);

@@ -79,7 +79,7 @@ void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s);
 void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s);
 
 // warp.hip
-void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], const float *ref_rgb,
+void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], float cmin, const float *ref_rgb,
                  const float *ref_depth, uint64_t *zbuf, float *tgt_rgb, float *tgt_depth, uint8_t *mask,
                  int32_t *src_index, int32_t *hole_idx, uint32_t *n_holes, hipStream_t s);
 void launch_sparw_finish(const uint32_t *n_holes, int64_t *n_masked, hipStream_t s);

@@ -13,9 +13,46 @@ namespace cic {
 
 __device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
 
-__global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera tgt, float T0, float T1, float T2,
-                                                    float T3, float T4, float T5, float T6, float T7, float T8,
-                                                    float T9, float T10, float T11, const float *ref_depth,
+// Reference -> target rigid transform, row-major 3x4.
+struct WarpT {
+    float m[12];
+};
+
+// Eq. 1-2 for reference pixel (i, j) at depth D: back-project, then move into
+// target-camera coordinates.  A point at infinity moves by the rotation only
+// and keeps depth +inf for the z-test.
+__device__ __forceinline__ void warp_point(const cic_camera &ref, const WarpT &T, int i, int j, float D, float &Xt,
+                                           float &Yt, float &Zt, float &kz)
+{
+    const float a = (((float)i + 0.5f) - ref.cx) / ref.f;
+    const float b = (((float)j + 0.5f) - ref.cy) / ref.f;
+    if (D == INFINITY) {
+        Xt = (T.m[0] * a + T.m[1] * b) + T.m[2];
+        Yt = (T.m[4] * a + T.m[5] * b) + T.m[6];
+        Zt = (T.m[8] * a + T.m[9] * b) + T.m[10];
+        kz = INFINITY;
+    } else {
+        const float X = D * a, Y = D * b, Z = D;
+        Xt = ((T.m[0] * X + T.m[1] * Y) + T.m[2] * Z) + T.m[3];
+        Yt = ((T.m[4] * X + T.m[5] * Y) + T.m[6] * Z) + T.m[7];
+        Zt = ((T.m[8] * X + T.m[9] * Y) + T.m[10] * Z) + T.m[11];
+        kz = Zt;
+    }
+}
+
+// Angle test of Sec. III-C in target-camera coordinates (target centre at
+// the origin, reference centre at the translation of T): cos of the angle the
+// two rays subtend at the point must exceed cmin.
+__device__ __forceinline__ bool angle_ok(float Xt, float Yt, float Zt, const WarpT &T, float cmin)
+{
+    const float rx = Xt - T.m[3], ry = Yt - T.m[7], rz = Zt - T.m[11];
+    const float dot = (Xt * rx + Yt * ry) + Zt * rz;
+    const float n1 = sqrtf((Xt * Xt + Yt * Yt) + Zt * Zt);
+    const float n2 = sqrtf((rx * rx + ry * ry) + rz * rz);
+    return dot / (n1 * n2) > cmin;
+}
+
+__global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera tgt, WarpT T, const float *ref_depth,
                                                     unsigned long long *zbuf)
 {
     const int64_t src = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -23,22 +60,8 @@ __global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera t
     if (src >= n) return;
     const float D = ref_depth[src];
     if (D != D) return;
-    const int i = (int)(src % ref.width), j = (int)(src / ref.width);
-    const float a = (((float)i + 0.5f) - ref.cx) / ref.f;
-    const float b = (((float)j + 0.5f) - ref.cy) / ref.f;
     float Xt, Yt, Zt, kz;
-    if (D == INFINITY) {
-        Xt = (T0 * a + T1 * b) + T2;
-        Yt = (T4 * a + T5 * b) + T6;
-        Zt = (T8 * a + T9 * b) + T10;
-        kz = INFINITY;
-    } else {
-        const float X = D * a, Y = D * b, Z = D;
-        Xt = ((T0 * X + T1 * Y) + T2 * Z) + T3;
-        Yt = ((T4 * X + T5 * Y) + T6 * Z) + T7;
-        Zt = ((T8 * X + T9 * Y) + T10 * Z) + T11;
-        kz = Zt;
-    }
+    warp_point(ref, T, (int)(src % ref.width), (int)(src / ref.width), D, Xt, Yt, Zt, kz);
     if (!(Zt > 0.0f)) return;
     const float u = tgt.f * (Xt / Zt) + tgt.cx;
     const float v = tgt.f * (Yt / Zt) + tgt.cy;
@@ -48,16 +71,29 @@ __global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera t
     atomicMin(&zbuf[p], key);
 }
 
-// Resolve: copy the winning reference pixel, or mark a hole and append it to
-// the hole list (one atomic per wavefront).
-__global__ __launch_bounds__(256) void k_warp_resolve(int64_t np, const unsigned long long *zbuf, const float *ref_rgb,
-                                                      float *tgt_rgb, float *tgt_depth, uint8_t *mask,
-                                                      int32_t *src_index, int32_t *hole_idx, uint32_t *n_holes)
+// Resolve: the z-buffer winner is the visible reference point.  With the
+// angle test on (cmin >= -1) a finite winner that fails it makes the pixel a
+// hole, as does an empty z-buffer entry.  Holes are appended to the hole list
+// with one atomic per wavefront.
+__global__ __launch_bounds__(256) void k_warp_resolve(int64_t np, const unsigned long long *zbuf, cic_camera ref,
+                                                      WarpT T, float cmin, const float *ref_depth,
+                                                      const float *ref_rgb, float *tgt_rgb, float *tgt_depth,
+                                                      uint8_t *mask, int32_t *src_index, int32_t *hole_idx,
+                                                      uint32_t *n_holes)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < np;
-    const unsigned long long key = in ? zbuf[p] : 0ull;
-    const bool hole = in && key == ~0ull;
+    const unsigned long long key = in ? zbuf[p] : ~0ull;
+    const uint32_t s = (uint32_t)(key & 0xffffffffull);
+    bool hole = in && key == ~0ull;
+    if (in && !hole && cmin >= -1.0f) {
+        const float D = ref_depth[s];
+        if (D != INFINITY) {
+            float Xt, Yt, Zt, kz;
+            warp_point(ref, T, (int)(s % (uint32_t)ref.width), (int)(s / (uint32_t)ref.width), D, Xt, Yt, Zt, kz);
+            hole = !angle_ok(Xt, Yt, Zt, T, cmin);
+        }
+    }
     if (in) {
         if (hole) {
             tgt_rgb[3 * p] = tgt_rgb[3 * p + 1] = tgt_rgb[3 * p + 2] = 0.f;
@@ -65,7 +101,6 @@ __global__ __launch_bounds__(256) void k_warp_resolve(int64_t np, const unsigned
             mask[p] = 1;
             if (src_index) src_index[p] = -1;
         } else {
-            const uint32_t s = (uint32_t)(key & 0xffffffffull);
             tgt_rgb[3 * p] = ref_rgb[3 * (int64_t)s];
             tgt_rgb[3 * p + 1] = ref_rgb[3 * (int64_t)s + 1];
             tgt_rgb[3 * p + 2] = ref_rgb[3 * (int64_t)s + 2];
@@ -86,20 +121,21 @@ __global__ __launch_bounds__(256) void k_warp_resolve(int64_t np, const unsigned
     }
 }
 
-void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], const float *ref_rgb,
+void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], float cmin, const float *ref_rgb,
                  const float *ref_depth, uint64_t *zbuf, float *tgt_rgb, float *tgt_depth, uint8_t *mask,
                  int32_t *src_index, int32_t *hole_idx, uint32_t *n_holes, hipStream_t s)
 {
     const int64_t nt = (int64_t)tgt.width * tgt.height;
     const int64_t nr = (int64_t)ref.width * ref.height;
+    WarpT wt;
+    for (int k = 0; k < 12; ++k) wt.m[k] = T[k];
     launch_fill_u64(zbuf, ~0ull, nt, s);
     if (n_holes) launch_fill_u32(n_holes, 0u, 1, s);
-    hipLaunchKernelGGL(k_warp_splat, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, ref, tgt, T[0], T[1], T[2],
-                       T[3], T[4], T[5], T[6], T[7], T[8], T[9], T[10], T[11], ref_depth,
+    hipLaunchKernelGGL(k_warp_splat, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, ref, tgt, wt, ref_depth,
                        (unsigned long long *)zbuf);
     hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, nt,
-                       (const unsigned long long *)zbuf, ref_rgb, tgt_rgb, tgt_depth, mask, src_index, hole_idx,
-                       n_holes);
+                       (const unsigned long long *)zbuf, ref, wt, cmin, ref_depth, ref_rgb, tgt_rgb, tgt_depth, mask,
+                       src_index, hole_idx, n_holes);
 }
 
 __global__ void k_sparw_finish(const uint32_t *n_holes, int64_t *n_masked)

@@ -99,15 +99,17 @@ def test_camera_and_warp_validation(L):
     bad = L.make_camera(0, 64, 80.0, 32.0, 32.0, [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 4])
     T = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
     p = C.c_void_p(0x5000)
-    rc = lib.warp_frame(C.byref(bad), C.byref(cam), T, p, p, p, p, p, None, p, C.c_size_t(1 << 30), None)
+    rc = lib.warp_frame(C.byref(bad), C.byref(cam), T, p, p, C.c_float(0), p, p, p, None, p, C.c_size_t(1 << 30), None)
     assert rc == -1 and "camera" in L.last_error()
-    rc = lib.warp_frame(C.byref(cam), C.byref(cam), None, p, p, p, p, p, None, p, C.c_size_t(1 << 30), None)
+    rc = lib.warp_frame(C.byref(cam), C.byref(cam), None, p, p, C.c_float(0), p, p, p, None, p, C.c_size_t(1 << 30), None)
     assert rc == -1
-    rc = lib.warp_frame(C.byref(cam), C.byref(cam), T, p, p, p, p, p, None, p, C.c_size_t(8), None)
+    rc = lib.warp_frame(C.byref(cam), C.byref(cam), T, p, p, C.c_float(0), p, p, p, None, p, C.c_size_t(8), None)
     assert rc == -2
     Tn = (C.c_float * 12)(1, 0, 0, float("nan"), 0, 1, 0, 0, 0, 0, 1, 0)
-    rc = lib.warp_frame(C.byref(cam), C.byref(cam), Tn, p, p, p, p, p, None, p, C.c_size_t(1 << 30), None)
+    rc = lib.warp_frame(C.byref(cam), C.byref(cam), Tn, p, p, C.c_float(0), p, p, p, None, p, C.c_size_t(1 << 30), None)
     assert rc == -1
+    rc = lib.warp_frame(C.byref(cam), C.byref(cam), T, p, p, C.c_float(-5), p, p, p, None, p, C.c_size_t(1 << 30), None)
+    assert rc == -1 and "max_angle" in L.last_error()
     rc = lib.generate_rays(C.byref(cam), C.c_int64(5), None, p, p, None)
     assert rc == -1 and "width*height" in L.last_error()
 

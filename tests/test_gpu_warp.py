@@ -111,3 +111,52 @@ def test_sparw_identity_renders_nothing_and_full_mask_renders_frame():
     assert int(nm.item()) == W * H
     assert torch.equal(rgb, ref_rgb)
     assert torch.equal(torch.nan_to_num(dz, posinf=-1), torch.nan_to_num(ref_dz, posinf=-1))
+
+
+@pytest.mark.parametrize("W,H,step,phi", [(64, 48, 8.0, 2.0), (800, 800, 6.0, 4.0), (800, 800, 15.0, 10.0)])
+def test_warp_angle_threshold_bit_exact(W, H, step, phi):
+    """Warp-angle test of Sec. III-C on: same float32 decision on both sides."""
+    import paper_2404_11852_amd as cic
+    print_case("warp angle %dx%d step %.0f phi %.1f" % (W, H, step, phi))
+    rgb, dep = _synthetic_ref(W, H, seed=int(step) + 3 * W)
+    rp, tp = synth.orbit_pose(0), synth.orbit_pose(1, step_deg=step)
+    gr, orr = cams(W, H, rp)
+    gt, ot = cams(W, H, tp)
+    T = _T(rp, tp)
+    g = cic.warp_frame(gr, gt, torch.from_numpy(T), torch.from_numpy(rgb).cuda(), torch.from_numpy(dep).cuda(),
+                       with_src=True, max_angle_deg=phi)
+    o = oracle.warp(orr, ot, T, rgb, dep, max_angle_deg=phi)
+    for a, b, name in zip(g, o, ("rgb", "depth", "mask", "src")):
+        assert np.array_equal(to_np(a), b), name
+    # the threshold removes splats (more holes than without it) but not all of them
+    o_off = oracle.warp(orr, ot, T, rgb, dep)
+    assert o[2].sum() >= o_off[2].sum()
+    assert o[2].sum() < W * H
+
+
+def test_sparw_angle_threshold_matches_oracle():
+    import paper_2404_11852_amd as cic
+    print_case("sparw angle 96x96")
+    W = H = 96
+    p = Pair(160, seed=2, mlp_seed=3, occupancy=True)
+    rp, tp = synth.orbit_pose(0), synth.orbit_pose(10)
+    gr, orr = cams(W, H, rp)
+    gt, ot = cams(W, H, tp)
+    oop = oracle.opts(256, 1e-4, True, warp_max_angle=3.0)
+    oop_off = oracle.opts(256, 1e-4, True)
+    ref_rgb, ref_dz, _, _ = oracle.render_pixels(p.orc, oop, orr)
+    ref_rgb32, ref_dz32 = ref_rgb.astype(np.float32), ref_dz.astype(np.float32)
+    T = _T(rp, tp)
+    go = cic.make_opts(256, 1e-4, True, warp_max_angle=3.0)
+    rgb, dz, mask, nm = cic.render_frame_sparw(p.gpu, go, gr, torch.from_numpy(ref_rgb32).cuda(),
+                                               torch.from_numpy(ref_dz32).cuda(), gt, torch.from_numpy(T))
+    orgb, odz, omask, onm = oracle.sparw(p.orc, oop, orr, ref_rgb32, ref_dz32, ot, T)
+    _, _, omask_off, onm_off = oracle.sparw(p.orc, oop_off, orr, ref_rgb32, ref_dz32, ot, T)
+    assert onm > onm_off
+    assert np.array_equal(to_np(mask), omask)
+    assert int(nm.item()) == onm
+    keep = omask == 0
+    assert np.array_equal(to_np(rgb)[keep].astype(np.float64), orgb[keep])
+    holes = np.nonzero(omask)[0]
+    _, _, _, diag = oracle.render_pixels(p.orc, oop, ot, holes)
+    compare(to_np(rgb)[holes], orgb[holes], margin=diag["margin"])

@@ -171,3 +171,92 @@ def test_mask_shrinks_as_target_approaches_reference(orc):
         fr.append(mask.mean())
     assert fr[-1] == 0.0
     assert all(a >= b for a, b in zip(fr, fr[1:])), fr
+
+
+def test_angle_threshold_limits(orc):
+    """Sec. III-C warp-angle test: 180 degrees equals no test; an identity
+    warp subtends no angle; points at infinity always pass."""
+    W, H = 48, 40
+    rng = np.random.default_rng(9)
+    rgb = rng.uniform(0, 1, (W * H, 3)).astype(np.float32)
+    dep = rng.uniform(2.0, 6.0, W * H).astype(np.float32)
+    dep[:100] = np.inf
+    rp, tp = synth.orbit_pose(0), synth.orbit_pose(1, step_deg=6.0)
+    cr, ct = _cam(orc, W, H, rp), _cam(orc, W, H, tp)
+    T = synth.relative_pose(synth.as_f32(rp), synth.as_f32(tp))
+    a = orc.warp(cr, ct, T, rgb, dep)
+    b = orc.warp(cr, ct, T, rgb, dep, max_angle_deg=180.0)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    c = orc.warp(cr, cr, _ident(), rgb, dep, max_angle_deg=0.5)
+    assert c[2].sum() == 0
+    allvoid = np.full(W * H, np.inf, np.float32)
+    d = orc.warp(cr, ct, T, rgb, allvoid, max_angle_deg=0.5)
+    e = orc.warp(cr, ct, T, rgb, allvoid)
+    assert np.array_equal(d[2], e[2])
+
+
+def test_angle_threshold_closed_form(orc):
+    """Plane at depth D seen by two cameras a baseline b apart along x: the
+    reference pixel whose point lies at x (reference camera frame) subtends
+    the angle between (x, y, D) and (x - b, y, D) at the point.  A target
+    pixel keeps the point the plain warp puts there when that point's angle
+    is below the threshold and becomes a hole otherwise.  Checked against
+    the float64 angle away from the boundary."""
+    W, H, D, f = 64, 48, 2.0, 40.0
+    cam = _cam(orc, W, H, synth.orbit_pose(0), f=f)
+    b = 0.25
+    T = _ident()
+    T[3] = -b          # target camera moved by +b along x
+    rng = np.random.default_rng(10)
+    rgb = rng.uniform(0, 1, (W * H, 3)).astype(np.float32)
+    dep = np.full(W * H, D, np.float32)
+    phi = 6.0
+    _, _, m_plain, src_plain = orc.warp(cam, cam, T, rgb, dep)
+    r_phi, _, m_phi, src_phi = orc.warp(cam, cam, T, rgb, dep, max_angle_deg=phi)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    x = (ii.ravel() + 0.5 - cam.cx) / f * D
+    y = (jj.ravel() + 0.5 - cam.cy) / f * D
+    # in target coordinates the point is (x - b, y, D), the reference centre (-b, 0, 0)
+    vt = np.stack([x - b, y, np.full_like(x, D)], 1)
+    vr = np.stack([x, y, np.full_like(x, D)], 1)
+    cosang = (vt * vr).sum(1) / (np.linalg.norm(vt, axis=1) * np.linalg.norm(vr, axis=1))
+    ang = np.degrees(np.arccos(np.clip(cosang, -1, 1)))
+    passes = ang < phi
+    covered = src_plain >= 0
+    s = src_plain[covered]
+    clear = np.abs(ang[s] - phi) > 1e-3
+    expect = np.where(passes[s], s, -1)
+    assert np.array_equal(src_phi[covered][clear], expect[clear])
+    assert np.all(src_phi[~covered] == -1)
+    assert 0 < passes[s].mean() < 1
+    hole = src_phi < 0
+    assert np.array_equal(m_phi.astype(bool), hole)
+    assert np.all(r_phi[hole] == 0)
+    assert np.array_equal(r_phi[~hole], rgb[src_phi[~hole]])
+
+
+def test_angle_threshold_nests(orc):
+    """A smaller threshold only adds holes: every pixel warped under the
+    smaller threshold is warped, from the same reference pixel, under the
+    larger one and without the test (quality can only rise as the threshold
+    falls, the trend of the paper's threshold sweep)."""
+    W, H = 64, 48
+    rng = np.random.default_rng(11)
+    rgb = rng.uniform(0, 1, (W * H, 3)).astype(np.float32)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    # two depth layers so that near points occlude far ones in the target
+    dep = np.where((ii // 8 + jj // 8) % 2 == 0, 2.0, 4.5).astype(np.float32).ravel()
+    dep[rng.uniform(size=W * H) < 0.05] = np.inf
+    rp, tp = synth.orbit_pose(0), synth.orbit_pose(1, step_deg=12.0)
+    cr, ct = _cam(orc, W, H, rp), _cam(orc, W, H, tp)
+    T = synth.relative_pose(synth.as_f32(rp), synth.as_f32(tp))
+    prev = orc.warp(cr, ct, T, rgb, dep)[3]
+    counts = [int((prev < 0).sum())]
+    for phi in (8.0, 5.0, 3.0, 1.0):
+        cur = orc.warp(cr, ct, T, rgb, dep, max_angle_deg=phi)[3]
+        kept = cur >= 0
+        assert np.array_equal(cur[kept], prev[kept])
+        counts.append(int((cur < 0).sum()))
+        prev = cur
+    assert counts == sorted(counts) and counts[-1] > counts[0]
