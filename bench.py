@@ -174,6 +174,48 @@ def sparw_sweep(model, opts, W, H, windows=(6, 16, 26), angles=(0.0, 8.0, 4.0, 2
     return base
 
 
+def sequence_bench(model, opts, W, H, n_frames=65, window=16):
+    """Off-trajectory references (Eq. 5-6) over an orbit: the two-stream
+    schedule against the serial one, and the paper's lead of half a window
+    against a lead that centres each reference on the window it serves.
+    Reports throughput, the frame clock (intervals between consecutive frame
+    completions) and PSNR against full renders."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    cams = [camera(W, H, synth.orbit_pose(k)) for k in range(n_frames)]
+    full = [cic.render_frame(model, opts, c)[0] for c in cams]
+    torch.cuda.synchronize()
+
+    def run(overlap, lead, part=0):
+        cic.render_sequence(model, opts, cams, window, lead=lead, overlap=overlap, target_cus_per_xcd=part)
+        torch.cuda.synchronize()
+        _lib.timing_enable(True)
+        t0 = time.perf_counter()
+        rgb, dz, mask, nm, refs = cic.render_sequence(model, opts, cams, window, lead=lead, overlap=overlap,
+                                                      target_cus_per_xcd=part)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        clock = _lib.timing_frames()
+        _lib.timing_enable(False)
+        iv = np.diff(np.array(clock))     # intervals between target frames (frame 0 reported apart)
+        ps = [psnr(rgb[k], full[k]) for k in range(1, n_frames)]
+        fr = (nm[1:].double() / (W * H)).cpu().numpy()
+        return {"overlap": overlap, "target_cus_per_xcd": part, "lead_frames": window / 2.0 if lead < 0 else lead,
+                "fps": n_frames / (t1 - t0), "ms_total": 1e3 * (t1 - t0), "frame0_ms": float(clock[0]),
+                "frame_interval_ms": {"p50": float(np.percentile(iv, 50)), "p95": float(np.percentile(iv, 95)),
+                                      "max": float(iv.max())},
+                "mask_fraction_mean": float(fr.mean()),
+                "psnr_vs_full_mean_db": float(np.mean(ps)), "psnr_vs_full_min_db": float(np.min(ps))}
+
+    res = {"frames": n_frames, "window": window, "references": 1 + (n_frames - 1 + window - 1) // window - 1,
+           "runs": [run(False, -1.0), run(True, -1.0), run(True, 1.5 * window)]
+           + [run(True, -1.0, t) for t in (16, 20, 24)] + [run(True, 1.5 * window, 20)]}
+    return res
+
+
 def precision_bench(scene, occ, steps):
     """Eight 800x800 views on the radius-4 sphere in one render_rays call:
     FP16 grids + BF16 MLP against the FP32 path on the same rays."""
@@ -418,6 +460,9 @@ def main():
     if not args.skip_sparw:
         log("SpaRW orbit")
         out["sparw"] = sparw_sweep(model, opts, W, H)
+    if not args.skip_sparw:
+        log("off-trajectory references, serial vs two streams")
+        out["sequence"] = sequence_bench(model, opts, W, H)
     if not args.skip_precision:
         log("precision path (8 views, FP16 grid + BF16 MLP)")
         out["precision"] = precision_bench(scene, model.occupancy, max(3, args.steps // 4))

@@ -70,7 +70,8 @@ enum {
     CIC_OP_RENDER_FRAME = 1,
     CIC_OP_WARP_FRAME = 2,
     CIC_OP_RENDER_FRAME_SPARW = 3,
-    CIC_OP_RENDER_BACKWARD = 4
+    CIC_OP_RENDER_BACKWARD = 4,
+    CIC_OP_RENDER_SEQUENCE = 5      /* n_items = pixels per frame */
 };
 
 typedef struct {
@@ -182,9 +183,10 @@ int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
  * is the translation of ref_T_tgt) leaves the pixel a hole, to be rendered;
  * points at infinity always pass.
  * Outputs (target size): tgt_rgb [H][W][3], tgt_depth_z [H][W] (+inf for
- * directions, 0 where nothing landed), mask [H][W] u8 (1 = nothing landed,
- * the disoccluded pixels to re-render), src_index [H][W] int32 (nullable;
- * reference pixel or -1).  Reference rgb/depth: [Hr][Wr][3], [Hr][Wr]. */
+ * directions, 0 at holes), mask [H][W] u8 (1 = hole to re-render: nothing
+ * landed, or the visible point failed the angle test), src_index [H][W]
+ * int32 (nullable; reference pixel or -1).  Reference rgb/depth:
+ * [Hr][Wr][3], [Hr][Wr]. */
 int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12],
                const float *ref_rgb, const float *ref_depth_z, float max_angle_deg,
                float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
@@ -202,6 +204,64 @@ int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts 
                        float *out_rgb, float *out_depth_z, uint8_t *mask,
                        int64_t *n_masked, int64_t *n_eval,
                        void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* Eq. 5-6 (Sec. III-C, reference frame rendering): the pose of an
+ * off-trajectory reference, extrapolated from the two newest camera poses.
+ * Poses are camera-to-world, row-major 3x4 [R | c], host float32.  The
+ * centre continues at the velocity (c_cur - c_prev) per frame interval for
+ * `steps` intervals (t_r = steps * dt); the orientation continues at the
+ * angular velocity that took R_prev to R_cur: the world-frame rotation
+ * R_cur R_prev^T raised to the power `steps` in axis-angle form, applied to
+ * R_cur.  float64 arithmetic, rounded once.  Host only, no device work.
+ * Errors: NULL pointer or non-finite value -> CIC_ERR_INVALID. */
+int cic_extrapolate_pose(const float c2w_prev[12], const float c2w_cur[12], float steps, float c2w_out[12]);
+
+/* Eq. 2's rigid transform from reference-camera to target-camera
+ * coordinates for camera-to-world poses: inverse(C2W_tgt) C2W_ref =
+ * [R_t^T R_r | R_t^T (c_r - c_t)], float64, rounded once (host only). */
+int cic_relative_pose(const float c2w_ref[12], const float c2w_tgt[12], float ref_T_tgt[12]);
+
+/* render_sequence flags */
+enum { CIC_SEQ_OVERLAP = 1 };
+
+/* A camera trajectory rendered with SpaRW and off-trajectory references
+ * (Sec. III-C, Eq. 5-6; Fig. 7 and 8 for the pipelines).
+ * Schedule: frame 0 is rendered in full and is reference R_0.  Frames
+ * 1..n_frames-1 form windows of `window` consecutive targets; window w
+ * starts at frame s_w = 1 + w*window and every target in it is rendered by
+ * render_frame_sparw from R_w.  R_{w+1} (w + 1 < number of windows) has the
+ * pose cic_extrapolate_pose(cams[s_w - 1], cams[s_w], lead), i.e. it needs
+ * only the poses known when window w starts; lead < 0 selects the paper's
+ * t_r = window/2 frame intervals.  References use the intrinsics of
+ * cams[s_w].
+ * flags & CIC_SEQ_OVERLAP: references render on a second stream owned by
+ * the library (one per device, default priority), concurrently with the
+ * previous window's targets (Fig. 8); the work stays ordered after
+ * everything issued to `stream` before the call, and `stream` waits for all
+ * of it before any later work.  Without the flag everything runs on
+ * `stream`, R_{w+1} after window w (Fig. 7a).  Both give identical results.
+ * target_cus_per_xcd > 0 (with CIC_SEQ_OVERLAP) partitions the chip as the
+ * paper splits the work between two engines: targets run on a library
+ * stream restricted to that many CUs of each XCD and references on a stream
+ * restricted to the rest (CU-masked streams, default priority, created once
+ * per device and split); the persistent kernels are sized to their share.
+ * Must be below the CUs per XCD (a multiple of 4 splits every shader
+ * engine evenly); 0 shares the whole chip.  Results are identical in every
+ * mode.
+ * cams: host array of n_frames cameras, all of one size with width*height
+ * <= 2^21.  Outputs (device, frame-major): rgb [n_frames][H*W][3],
+ * depth_z [n_frames][H*W], mask [n_frames][H*W] (1 = pixel rendered; all of
+ * frame 0), n_masked [n_frames] int64 (nullable; rendered pixels per frame),
+ * n_eval as in render_rays.  ref_c2w (host, nullable) receives the poses of
+ * R_1, R_2, ... ([n_windows - 1][12]).  Workspace:
+ * cic_workspace_bytes(CIC_OP_RENDER_SEQUENCE, H*W, ...).  Calls that share
+ * a device from several host threads at once are not supported. */
+int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
+                    const cic_camera *cams, int32_t n_frames, int32_t window, float lead, int32_t flags,
+                    int32_t target_cus_per_xcd,
+                    float *rgb, float *depth_z, uint8_t *mask, int64_t *n_masked,
+                    float *ref_c2w, int64_t *n_eval,
+                    void *ws, size_t ws_bytes, cic_stream_t stream);
 
 /* Adjoint of render_rays (the derivative of the same quadrature; the paper
  * itself is inference-only).  The forward is recomputed per ray; nothing
@@ -238,6 +298,12 @@ enum {
 };
 int cic_timing_enable(int on);
 int cic_timing_read(double *ms, int64_t *launches, int n_stages);
+
+/* Frame clock of the last render_sequence call made while timing was on:
+ * writes to ms (host, up to cap entries) the completion time of each frame,
+ * in milliseconds after the call's first work began on its stream, and
+ * returns the number of frames (or a negative error code). */
+int cic_timing_frames(double *ms, int cap);
 
 #ifdef __cplusplus
 }

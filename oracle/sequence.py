@@ -124,7 +124,7 @@ def render_sequence(model, op, width, height, f, cx, cy, c2ws, window, lead=None
     n_frames = len(cams)
     out = [None] * n_frames
     rgb0, dz0, _, _ = render_pixels(model, op, cams[0])
-    out[0] = (rgb0, dz0, np.zeros(width * height, np.uint8), 0)
+    out[0] = (rgb0, dz0, np.ones(width * height, np.uint8), width * height)   # every pixel rendered
     ref = (np.asarray(c2ws[0], np.float32).reshape(12), rgb0.astype(np.float32), dz0.astype(np.float32))
     poses = reference_poses(c2ws, window, lead)
     for w, s in enumerate(window_starts(n_frames, window)):

@@ -6,10 +6,12 @@ done by the HIP kernels behind the C interface in include/cicero.h.
 import torch
 
 from . import _lib
-from ._lib import (CIC_F16, CIC_F32, CIC_BF16, CIC_ORDER_RAY, CIC_ORDER_VOXEL, CicError, make_camera, make_opts)
+from ._lib import (CIC_F16, CIC_F32, CIC_BF16, CIC_ORDER_RAY, CIC_ORDER_VOXEL, CicError, extrapolate_pose,
+                   make_camera, make_opts, relative_pose)
 
 __all__ = ["Model", "make_camera", "make_opts", "CicError", "render_rays", "render_frame", "warp_frame",
-           "render_frame_sparw", "render_backward", "generate_rays", "build_occupancy", "RenderRays",
+           "render_frame_sparw", "render_sequence", "render_backward", "generate_rays", "build_occupancy",
+           "extrapolate_pose", "relative_pose", "RenderRays",
            "CIC_F32", "CIC_F16", "CIC_BF16", "CIC_ORDER_RAY", "CIC_ORDER_VOXEL"]
 
 
@@ -98,6 +100,24 @@ def render_frame_sparw(model, opts, ref_cam, ref_rgb, ref_depth, tgt_cam, T, n_e
     _lib.render_frame_sparw(model.grid, model.mlp, opts, ref_cam, ref_rgb.contiguous(), ref_depth.contiguous(),
                             tgt_cam, T, rgb, dz, mask, nm, n_eval)
     return rgb, dz, mask, nm
+
+
+def render_sequence(model, opts, cams, window, lead=-1.0, overlap=True, target_cus_per_xcd=0, n_eval=None):
+    """Render a trajectory (list of cameras of one size) with off-trajectory
+    references every `window` targets.  Returns rgb [F, P, 3], z-depth
+    [F, P], mask [F, P], rendered-pixel counts [F] and the reference poses
+    (list of 12-value rows)."""
+    n = len(cams)
+    npix = cams[0].width * cams[0].height
+    dev = model.device
+    rgb = torch.empty((n, npix, 3), dtype=torch.float32, device=dev)
+    dz = torch.empty((n, npix), dtype=torch.float32, device=dev)
+    mask = torch.empty((n, npix), dtype=torch.uint8, device=dev)
+    nm = torch.zeros(n, dtype=torch.int64, device=dev)
+    refs = _lib.render_sequence(model.grid, model.mlp, opts, cams, window, lead,
+                                _lib.CIC_SEQ_OVERLAP if overlap else 0, rgb, dz, mask, nm, n_eval,
+                                target_cus_per_xcd)
+    return rgb, dz, mask, nm, refs
 
 
 def render_backward(model, opts, rays_o, rays_d, d_rgb, d_depth_t=None, d_acc=None, grads=None):

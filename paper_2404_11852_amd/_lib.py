@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libcicero.so")
 
 CIC_F32, CIC_F16, CIC_BF16 = 0, 1, 2
 CIC_ORDER_RAY, CIC_ORDER_VOXEL = 0, 1
-OP_RENDER_RAYS, OP_RENDER_FRAME, OP_WARP_FRAME, OP_RENDER_FRAME_SPARW, OP_RENDER_BACKWARD = range(5)
+(OP_RENDER_RAYS, OP_RENDER_FRAME, OP_WARP_FRAME, OP_RENDER_FRAME_SPARW, OP_RENDER_BACKWARD,
+ OP_RENDER_SEQUENCE) = range(6)
+CIC_SEQ_OVERLAP = 1
 
 
 class CicError(RuntimeError):
@@ -51,7 +53,7 @@ class Camera(C.Structure):
 
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
            "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
-           "cic_timing_read"]
+           "cic_timing_read", "cic_extrapolate_pose", "cic_relative_pose", "render_sequence", "cic_timing_frames"]
 STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad", "embed"]
 
 _lib = None
@@ -82,6 +84,11 @@ def lib():
                                               vp, vp, u64, vp]
                 L.cic_timing_enable.argtypes = [C.c_int]
                 L.cic_timing_read.argtypes = [vp, vp, C.c_int]
+                L.cic_extrapolate_pose.argtypes = [vp, vp, f, vp]
+                L.cic_relative_pose.argtypes = [vp, vp, vp]
+                L.render_sequence.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, f, C.c_int32, C.c_int32, vp,
+                                              vp, vp, vp, vp, vp, vp, u64, vp]
+                L.cic_timing_frames.argtypes = [vp, C.c_int]
                 for name in EXPORTS[2:]:
                     getattr(L, name).restype = C.c_int
                 _lib = L
@@ -244,3 +251,51 @@ def timing_read():
     cnt = (C.c_int64 * n)()
     _check(lib().cic_timing_read(ms, cnt, n))
     return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def _pose12(p):
+    a = (C.c_float * 12)()
+    v = [float(x) for x in (p.reshape(-1).tolist() if hasattr(p, "reshape") else list(p))]
+    if len(v) != 12:
+        raise CicError(-1, "a pose has 12 values (row-major 3x4)")
+    a[:] = v
+    return a
+
+
+def extrapolate_pose(c2w_prev, c2w_cur, steps):
+    out = (C.c_float * 12)()
+    _check(lib().cic_extrapolate_pose(_pose12(c2w_prev), _pose12(c2w_cur), C.c_float(steps), out))
+    return list(out)
+
+
+def relative_pose(c2w_ref, c2w_tgt):
+    out = (C.c_float * 12)()
+    _check(lib().cic_relative_pose(_pose12(c2w_ref), _pose12(c2w_tgt), out))
+    return list(out)
+
+
+def render_sequence(grid, mlp, opts, cams, window, lead, flags, rgb, depth_z, mask, n_masked=None, n_eval=None,
+                    target_cus_per_xcd=0):
+    """cams: sequence of Camera structs; returns the reference poses."""
+    n = len(cams)
+    arr = (Camera * max(n, 1))(*cams)
+    n_win = (n - 1 + window - 1) // window if n > 1 and window > 0 else 0
+    refs = (C.c_float * (12 * max(n_win - 1, 1)))()
+    npix = cams[0].width * cams[0].height if n else 0
+    nb = workspace_bytes(OP_RENDER_SEQUENCE, npix, grid, opts)
+    ws = workspace(nb, rgb.device)
+    _check(lib().render_sequence(C.byref(grid), C.byref(mlp), C.byref(opts), arr, C.c_int32(n), C.c_int32(window),
+                                 C.c_float(lead), C.c_int32(flags), C.c_int32(target_cus_per_xcd), _ptr(rgb),
+                                 _ptr(depth_z), _ptr(mask),
+                                 _ptr(n_masked), refs, _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()), _stream()))
+    return [list(refs[12 * i:12 * i + 12]) for i in range(max(n_win - 1, 0))]
+
+
+def timing_frames(cap=4096):
+    """Completion times (ms) of the frames of the last render_sequence call
+    made while timing was on."""
+    ms = (C.c_double * cap)()
+    n = lib().cic_timing_frames(ms, cap)
+    if n < 0:
+        raise CicError(n, last_error())
+    return list(ms[:min(n, cap)])

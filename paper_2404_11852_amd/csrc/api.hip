@@ -203,6 +203,28 @@ WarpBufs carve_warp(Carver &cv, int64_t np, bool holes)
     return w;
 }
 
+// render_sequence: warp + sparse-render buffers for the target stream,
+// render buffers for the reference stream, two reference frame slots.
+struct SeqBufs {
+    WarpBufs w;
+    RenderBufs a, b;
+    float *ref_rgb[2], *ref_dz[2];
+};
+
+SeqBufs carve_seq(Carver &cv, int64_t np, const cic_opts *o, int64_t nb)
+{
+    SeqBufs q{};
+    const bool voxel = o->order == CIC_ORDER_VOXEL;
+    q.w = carve_warp(cv, np, true);
+    q.a = carve_render(cv, np, o->n_samples, nb, voxel, true);
+    q.b = carve_render(cv, np, o->n_samples, nb, voxel, true);
+    for (int k = 0; k < 2; ++k) {
+        q.ref_rgb[k] = cv.take<float>(3 * np);
+        q.ref_dz[k] = cv.take<float>(np);
+    }
+    return q;
+}
+
 constexpr int64_t kChunkRaysBwd = 4096;
 
 // Extra buffers of a backward pass (after carve_render's).
@@ -235,6 +257,9 @@ size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
     case CIC_OP_RENDER_FRAME_SPARW:
         carve_warp(cv, n, true);
         carve_render(cv, n, o->n_samples, nb, voxel, true);
+        break;
+    case CIC_OP_RENDER_SEQUENCE:
+        carve_seq(cv, n, o, nb);
         break;
     case CIC_OP_RENDER_BACKWARD: {
         const int64_t nc = n < kChunkRaysBwd ? n : kChunkRaysBwd;
@@ -298,6 +323,15 @@ struct Timing {
     bool on = false;
     std::vector<TimedLaunch> recs;
     std::vector<hipEvent_t> pool;
+    hipEvent_t frame0 = nullptr;          // frame clock of the last render_sequence
+    std::vector<hipEvent_t> frames;
+    void reset_frames()
+    {
+        if (frame0) pool.push_back(frame0);
+        frame0 = nullptr;
+        for (auto e : frames) pool.push_back(e);
+        frames.clear();
+    }
     hipEvent_t get()
     {
         if (!pool.empty()) {
@@ -374,6 +408,142 @@ void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, con
     {
         StageTimer t(CIC_STAGE_REDUCE, s);
         launch_reduce(b, ok_, rgb, depth, acc, out_map, frame_cam, n_eval, s);
+    }
+}
+
+// Full render of one frame that fits one pass (np <= kChunkRays); b carved
+// with generated rays.
+void full_frame(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, const OptsK &ok_, bool voxel,
+                RenderBufs b, const cic_camera &cam, float *rgb, float *depth_z, int64_t *n_eval, hipStream_t s)
+{
+    const int64_t np = (int64_t)cam.width * cam.height;
+    b.n_active = nullptr;
+    {
+        StageTimer t(CIC_STAGE_RAYGEN, s);
+        launch_generate_rays(cam, np, 0, nullptr, nullptr, nullptr, (float *)b.rays_o, (float *)b.rays_d, s);
+    }
+    run_pipeline(grid, gk, mlp, ok_, voxel, b, rgb, depth_z, nullptr, nullptr, &cam, n_eval, s);
+}
+
+// Warp from a reference, then render the holes in place (Eq. 4).
+void sparw_frame(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, const cic_opts *opts, const OptsK &ok_,
+                 bool voxel, const WarpBufs &w, RenderBufs b, const cic_camera &ref, const float *ref_rgb,
+                 const float *ref_dz, const cic_camera &tgt, const float T[12], float *out_rgb, float *out_dz,
+                 uint8_t *mask, int64_t *n_masked, int64_t *n_eval, hipStream_t s)
+{
+    const int64_t np = (int64_t)tgt.width * tgt.height;
+    b.n_active = w.n_holes;
+    {
+        StageTimer t(CIC_STAGE_WARP, s);
+        launch_warp(ref, tgt, T, cos_limit(opts->warp_max_angle), ref_rgb, ref_dz, w.zbuf, out_rgb, out_dz, mask,
+                    nullptr, w.hole_idx, w.n_holes, s);
+    }
+    {
+        StageTimer t(CIC_STAGE_RAYGEN, s);
+        launch_generate_rays(tgt, np, 0, nullptr, w.hole_idx, w.n_holes, (float *)b.rays_o, (float *)b.rays_d, s);
+    }
+    run_pipeline(grid, gk, mlp, ok_, voxel, b, out_rgb, out_dz, nullptr, w.hole_idx, &tgt, n_eval, s);
+    if (n_masked) launch_sparw_finish(w.n_holes, n_masked, s);
+}
+
+// The library's second stream per device (default priority, non-blocking)
+// and the events that order it against the caller's stream.
+struct SideSync {
+    bool ready = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t start = nullptr, side_end = nullptr, f0 = nullptr, win_end[2] = {}, ref_ready[2] = {};
+};
+std::mutex g_side_mu;
+SideSync g_side[64];
+
+int side_sync(SideSync **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "no HIP device");
+    }
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideSync &x = g_side[dev];
+    if (!x.ready) {
+        bool good = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking) == hipSuccess;
+        hipEvent_t *evs[] = {&x.start, &x.side_end, &x.f0, &x.win_end[0], &x.win_end[1], &x.ref_ready[0],
+                             &x.ref_ready[1]};
+        for (hipEvent_t *e : evs) good = good && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        if (!good) {
+            (void)hipGetLastError();
+            return fail(CIC_ERR_HIP, "could not create the reference stream or its events");
+        }
+        x.ready = true;
+    }
+    *out = &x;
+    return CIC_OK;
+}
+
+// CU-partitioned stream pair for render_sequence: per XCD, `t` CUs for the
+// targets and the rest for the references.  The driver spreads the bits of a
+// stream's CU mask over the chip interleaved: bit i goes to XCD i % 8, and
+// within the XCD bit i / 8 goes to shader engine (i / 8) % 4.  The targets
+// take bits [0, 8t) and the references the rest, so every XCD gets t target
+// CUs, and with t a multiple of 4 every shader engine gets the same number
+// (the dispatcher deals workgroups to the shader engines in turn, so an
+// uneven split would leave the persistent kernels' last workgroups waiting).
+constexpr int kXcdCount = 8;
+struct PartStreams {
+    int t = 0;
+    hipStream_t tgt = nullptr, ref = nullptr;
+};
+std::vector<PartStreams> g_part[64];
+
+int device_cus(int *n)
+{
+    int dev = 0;
+    *n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "could not read the CU count");
+    }
+    return CIC_OK;
+}
+
+int part_streams(int t, PartStreams *out)
+{
+    int dev = 0, ncu = 0, rc;
+    if ((rc = device_cus(&ncu))) return rc;
+    (void)hipGetDevice(&dev);
+    const int per = ncu / kXcdCount;
+    if (ncu % kXcdCount != 0 || per % kXcdCount != 0 || ncu > 1024)
+        return fail(CIC_ERR_INVALID, "CU partitioning needs 8 XCDs of a multiple of 8 CUs (device has %d CUs)", ncu);
+    if (t < 1 || t >= per) return fail(CIC_ERR_INVALID, "target_cus_per_xcd=%d outside [1,%d]", t, per - 1);
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    for (auto &p : g_part[dev])
+        if (p.t == t) {
+            *out = p;
+            return CIC_OK;
+        }
+    uint32_t mt[32] = {}, mr[32] = {};
+    for (int bit = 0; bit < ncu; ++bit) (bit < kXcdCount * t ? mt : mr)[bit / 32] |= 1u << (bit % 32);
+    PartStreams p;
+    p.t = t;
+    const uint32_t words = (uint32_t)((ncu + 31) / 32);
+    if (hipExtStreamCreateWithCUMask(&p.tgt, words, mt) != hipSuccess ||
+        hipExtStreamCreateWithCUMask(&p.ref, words, mr) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "could not create CU-masked streams");
+    }
+    g_part[dev].push_back(p);
+    *out = p;
+    return CIC_OK;
+}
+
+void frame_mark(hipStream_t s)
+{
+    if (!g_timing.on) return;
+    hipEvent_t e = g_timing.get();
+    if (e) {
+        (void)hipEventRecord(e, s);
+        g_timing.frames.push_back(e);
     }
 }
 
@@ -541,19 +711,133 @@ int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts 
     Carver cv(align_ws(ws));
     WarpBufs w = carve_warp(cv, np, true);
     RenderBufs b = carve_render(cv, np, opts->n_samples, n_bricks_of(grid), voxel, true);
-    b.n_active = w.n_holes;
-    {
-        StageTimer t(CIC_STAGE_WARP, s);
-        launch_warp(*ref, *tgt, ref_T_tgt, cos_limit(opts->warp_max_angle), ref_rgb, ref_depth_z, w.zbuf, out_rgb,
-                    out_depth_z, mask, nullptr, w.hole_idx, w.n_holes, s);
-    }
-    {
-        StageTimer t(CIC_STAGE_RAYGEN, s);
-        launch_generate_rays(*tgt, np, 0, nullptr, w.hole_idx, w.n_holes, (float *)b.rays_o, (float *)b.rays_d, s);
-    }
-    run_pipeline(grid, gk, mlp, ok_, voxel, b, out_rgb, out_depth_z, nullptr, w.hole_idx, tgt, n_eval, s);
-    if (n_masked) launch_sparw_finish(w.n_holes, n_masked, s);
+    sparw_frame(grid, gk, mlp, opts, ok_, voxel, w, b, *ref, ref_rgb, ref_depth_z, *tgt, ref_T_tgt, out_rgb,
+                out_depth_z, mask, n_masked, n_eval, s);
     return after_launch("render_frame_sparw");
+}
+
+int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cams,
+                    int32_t n_frames, int32_t window, float lead, int32_t flags, int32_t target_cus_per_xcd,
+                    float *rgb, float *depth_z, uint8_t *mask, int64_t *n_masked, float *ref_c2w, int64_t *n_eval,
+                    void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
+    if (n_frames < 0) return fail(CIC_ERR_INVALID, "n_frames < 0");
+    if (n_frames == 0) return ok();
+    if (window < 1) return fail(CIC_ERR_INVALID, "window must be >= 1");
+    if (!finite_f(lead)) return fail(CIC_ERR_INVALID, "lead is not finite");
+    if ((flags & ~CIC_SEQ_OVERLAP) != 0) return fail(CIC_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (target_cus_per_xcd < 0 || (target_cus_per_xcd > 0 && !(flags & CIC_SEQ_OVERLAP)))
+        return fail(CIC_ERR_INVALID, "target_cus_per_xcd needs CIC_SEQ_OVERLAP and must be >= 0");
+    if (!cams) return fail(CIC_ERR_INVALID, "cams is NULL");
+    for (int32_t k = 0; k < n_frames; ++k) {
+        if ((rc = check_camera(&cams[k], "sequence"))) return rc;
+        if (cams[k].width != cams[0].width || cams[k].height != cams[0].height)
+            return fail(CIC_ERR_INVALID, "camera %d has another size than camera 0", k);
+    }
+    if (!rgb || !depth_z || !mask) return fail(CIC_ERR_INVALID, "frame pointer is NULL");
+    const int64_t np = (int64_t)cams[0].width * cams[0].height;
+    if (np > kChunkRays)
+        return fail(CIC_ERR_INVALID, "frame has %lld pixels; at most %lld", (long long)np, (long long)kChunkRays);
+    const size_t need = bytes_for(CIC_OP_RENDER_SEQUENCE, np, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+
+    // reference poses (host): R_0 = frame 0, R_{w+1} from the poses known when window w starts
+    const int32_t n_win = (n_frames - 1 + window - 1) / window;
+    const float steps = lead < 0.f ? 0.5f * (float)window : lead;
+    std::vector<cic_camera> refs((size_t)(n_win > 0 ? n_win : 1));
+    refs[0] = cams[0];
+    for (int32_t w = 0; w + 1 < n_win; ++w) {
+        const int32_t sw = 1 + w * window;
+        refs[w + 1] = cams[sw];
+        if (cic_extrapolate_pose(cams[sw - 1].c2w, cams[sw].c2w, steps, refs[w + 1].c2w) != CIC_OK)
+            return fail(CIC_ERR_INVALID, "pose extrapolation failed for reference %d", w + 1);
+        if ((rc = check_camera(&refs[w + 1], "extrapolated reference"))) return rc;
+        if (ref_c2w) memcpy(ref_c2w + 12 * (size_t)w, refs[w + 1].c2w, 12 * sizeof(float));
+    }
+
+    const bool overlap = (flags & CIC_SEQ_OVERLAP) != 0;
+    SideSync *ss = nullptr;
+    if (overlap && (rc = side_sync(&ss))) return rc;
+    PartStreams ps;
+    if (target_cus_per_xcd > 0 && (rc = part_streams(target_cus_per_xcd, &ps))) return rc;
+    const bool part = target_cus_per_xcd > 0;
+    hipStream_t caller = (hipStream_t)stream;
+    // s: targets, sb: references
+    hipStream_t s = part ? ps.tgt : caller;
+    hipStream_t sb = part ? ps.ref : (overlap ? ss->stream : caller);
+    const bool voxel = opts->order == CIC_ORDER_VOXEL;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    Carver cv(align_ws(ws));
+    SeqBufs q = carve_seq(cv, np, opts, n_bricks_of(grid));
+    if (part) {
+        int ncu = 0;
+        if ((rc = device_cus(&ncu))) return rc;
+        q.a.grid_cus = kXcdCount * target_cus_per_xcd;
+        q.b.grid_cus = ncu - q.a.grid_cus;
+    }
+    auto ref_rgb = [&](int32_t w) -> const float * { return w == 0 ? rgb : q.ref_rgb[w & 1]; };
+    auto ref_dz = [&](int32_t w) -> const float * { return w == 0 ? depth_z : q.ref_dz[w & 1]; };
+    auto render_ref = [&](int32_t w, hipStream_t st) {
+        full_frame(grid, gk, mlp, ok_, voxel, q.b, refs[w], q.ref_rgb[w & 1], q.ref_dz[w & 1], n_eval, st);
+    };
+
+    if (g_timing.on) {
+        g_timing.reset_frames();
+        g_timing.frame0 = g_timing.get();
+        if (g_timing.frame0) (void)hipEventRecord(g_timing.frame0, caller);
+    }
+    if (overlap) {
+        (void)hipEventRecord(ss->start, caller);
+        (void)hipStreamWaitEvent(sb, ss->start, 0);
+        if (part) (void)hipStreamWaitEvent(s, ss->start, 0);
+    }
+    // frame 0: rendered in full; it is R_0
+    full_frame(grid, gk, mlp, ok_, voxel, q.a, cams[0], rgb, depth_z, n_eval, s);
+    launch_fill_u8(mask, 1, np, s);
+    if (n_masked) launch_fill_u64((uint64_t *)n_masked, (uint64_t)np, 1, s);
+    frame_mark(s);
+    if (overlap) (void)hipEventRecord(ss->f0, s);
+
+    for (int32_t w = 0; w < n_win; ++w) {
+        if (overlap) {
+            // R_{w+1} renders on the side stream once the poses it needs are known (the frames
+            // before window w are done); its slot was last read by window w - 1.
+            if (w + 1 < n_win) {
+                (void)hipStreamWaitEvent(sb, w == 0 ? ss->f0 : ss->win_end[(w - 1) & 1], 0);
+                render_ref(w + 1, sb);
+                (void)hipEventRecord(ss->ref_ready[(w + 1) & 1], sb);
+            }
+            if (w >= 1) (void)hipStreamWaitEvent(s, ss->ref_ready[w & 1], 0);
+        } else if (w >= 1) {
+            render_ref(w, s);
+        }
+        const int32_t first = 1 + w * window;
+        const int32_t last = first + window < n_frames ? first + window : n_frames;
+        for (int32_t k = first; k < last; ++k) {
+            float T[12];
+            if (cic_relative_pose(refs[w].c2w, cams[k].c2w, T) != CIC_OK)
+                return fail(CIC_ERR_INVALID, "relative pose failed for frame %d", k);
+            sparw_frame(grid, gk, mlp, opts, ok_, voxel, q.w, q.a, refs[w], ref_rgb(w), ref_dz(w), cams[k], T,
+                        rgb + 3 * np * k, depth_z + np * k, mask + np * k, n_masked ? n_masked + k : nullptr,
+                        n_eval, s);
+            frame_mark(s);
+        }
+        if (overlap) (void)hipEventRecord(ss->win_end[w & 1], s);
+    }
+    if (overlap) {
+        (void)hipEventRecord(ss->side_end, sb);
+        (void)hipStreamWaitEvent(caller, ss->side_end, 0);
+        if (part) {
+            // the target stream's last work, reusing the first window's end event
+            (void)hipEventRecord(ss->win_end[0], s);
+            (void)hipStreamWaitEvent(caller, ss->win_end[0], 0);
+        }
+    }
+    return after_launch("render_sequence");
 }
 
 int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
@@ -632,6 +916,7 @@ int cic_timing_enable(int on)
         g_timing.pool.push_back(r.b);
     }
     g_timing.recs.clear();
+    g_timing.reset_frames();
     g_timing.on = on != 0;
     return ok();
 }
@@ -653,6 +938,21 @@ int cic_timing_read(double *ms, int64_t *launches, int n_stages)
         }
     }
     return ok();
+}
+
+int cic_timing_frames(double *ms, int cap)
+{
+    if (cap < 0 || (cap > 0 && !ms)) return fail(CIC_ERR_INVALID, "bad frame-clock array");
+    const int n = (int)g_timing.frames.size();
+    if (n == 0 || !g_timing.frame0) return 0;
+    for (int i = 0; i < n && i < cap; ++i) {
+        if (hipEventSynchronize(g_timing.frames[i]) != hipSuccess) return fail(CIC_ERR_HIP, "hipEventSynchronize failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, g_timing.frame0, g_timing.frames[i]) != hipSuccess)
+            return fail(CIC_ERR_HIP, "hipEventElapsedTime failed");
+        ms[i] = t;
+    }
+    return n;
 }
 
 }  // extern "C"

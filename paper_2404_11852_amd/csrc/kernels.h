@@ -40,6 +40,8 @@ struct RenderBufs {
     uint32_t *brick_tmp;   // block sums for the brick scan
     uint32_t *perm;        // [n*N] sample order for the MLP stage
     int64_t n_bricks;
+    int grid_cus;          // CUs the launch stream may use, a multiple of 8 (0 = the whole device): sizes the
+                           // persistent kernels' grids
 };
 
 // Per-sample row of MLP vectors kept for the weight gradients (adjoint):
@@ -60,6 +62,7 @@ void launch_compact(const GridK &g, const RenderBufs &b, bool voxel_keys, hipStr
 void launch_brick_scatter(const RenderBufs &b, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 // Final per-ray accumulation.  out_map (nullable) maps ray -> output slot;
 // frame_cam (nullable) switches depth output to frame z-depth.
 void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,

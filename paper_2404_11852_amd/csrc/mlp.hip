@@ -578,8 +578,9 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
     }
 }
 
-static int num_cus()
+static int num_cus(const RenderBufs &b)
 {
+    if (b.grid_cus > 0) return b.grid_cus;
     int dev = 0, n = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
@@ -596,7 +597,7 @@ static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bo
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE, PET>), dim3(num_cus()), dim3(kMlpWaves * 64), lds, s, g, m, b,
+    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE, PET>), dim3(num_cus(b)), dim3(kMlpWaves * 64), lds, s, g, m, b,
                        voxel ? 1 : 0);
 }
 
@@ -609,7 +610,7 @@ static void launch_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, b
                                   kLdsBf16);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus() * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
+    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus(b) * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
                        voxel ? 1 : 0);
 }
 

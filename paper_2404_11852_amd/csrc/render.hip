@@ -238,6 +238,15 @@ void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
 }
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u8, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
 
 // Per-ray accumulation: rgb = sum_k w_k c_k + T_stop bg, depth_t,
 // acc = 1 - T_stop; frame mode converts to z-depth with the void rule.  One
