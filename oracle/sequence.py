@@ -137,3 +137,55 @@ def render_sequence(model, op, width, height, f, cx, cy, c2ws, window, lead=None
             T = relative_pose(ref[0], c2ws[k])
             out[k] = sparw(model, op, ref_cam, ref[1], ref[2], cams[k], T)
     return out, poses
+
+
+# ---------------------------------------------------------------------------
+# comparison variants of the paper's evaluation
+# ---------------------------------------------------------------------------
+def low_res_camera(width, height, f, cx, cy, factor):
+    """Camera of the same pose whose pixels are `factor` times larger:
+    ceil(W/s) x ceil(H/s) pixels, f/s, principal point /s (float32)."""
+    s = np.float32(factor)
+    return ((width + factor - 1) // factor, (height + factor - 1) // factor,
+            float(np.float32(f) / s), float(np.float32(cx) / s), float(np.float32(cy) / s))
+
+
+def upsample_bilinear(img, w, h, width, height, factor):
+    """Bilinear upsampling of a [h*w, C] image to [height*width, C]: output
+    pixel centre i + 1/2 sits at (i + 1/2)/s - 1/2 in low-resolution pixel
+    index space; neighbours outside the image are clamped to the border."""
+    img = np.asarray(img, np.float64).reshape(h, w, -1)
+    x = (np.arange(width) + 0.5) / factor - 0.5
+    y = (np.arange(height) + 0.5) / factor - 0.5
+    x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
+    fx, fy = x - x0, y - y0
+    xa, xb = np.clip(x0, 0, w - 1), np.clip(x0 + 1, 0, w - 1)
+    ya, yb = np.clip(y0, 0, h - 1), np.clip(y0 + 1, 0, h - 1)
+    top = img[ya][:, xa] * (1 - fx)[None, :, None] + img[ya][:, xb] * fx[None, :, None]
+    bot = img[yb][:, xa] * (1 - fx)[None, :, None] + img[yb][:, xb] * fx[None, :, None]
+    out = top * (1 - fy)[:, None, None] + bot * fy[:, None, None]
+    return out.reshape(height * width, -1)
+
+
+def render_downsampled(model, op, width, height, f, cx, cy, c2w, factor=2):
+    """DS-s variant: render at 1/s resolution, upsample bilinearly (rgb)."""
+    w, h, fl, cxl, cyl = low_res_camera(width, height, f, cx, cy, factor)
+    rgb, _, _, diag = render_pixels(model, op, camera(w, h, fl, cxl, cyl, np.asarray(c2w, np.float32).reshape(12)))
+    return upsample_bilinear(rgb, w, h, width, height, factor), rgb, diag
+
+
+def render_temporal(model, op, width, height, f, cx, cy, c2ws, window):
+    """Temp-N variant: frames 0, N, 2N, ... are rendered in full; every other
+    frame is warped from the previous output frame (its colour and z-depth,
+    as float32) with the holes rendered, so warping errors carry forward."""
+    cams = [camera(width, height, f, cx, cy, np.asarray(p, np.float32).reshape(12)) for p in c2ws]
+    out = []
+    for k, cam in enumerate(cams):
+        if k % window == 0:
+            rgb, dz, _, _ = render_pixels(model, op, cam)
+            out.append((rgb, dz, np.ones(width * height, np.uint8), width * height))
+        else:
+            prgb, pdz = out[k - 1][0].astype(np.float32), out[k - 1][1].astype(np.float32)
+            T = relative_pose(c2ws[k - 1], c2ws[k])
+            out.append(sparw(model, op, cams[k - 1], prgb, pdz, cam, T))
+    return out

@@ -121,3 +121,70 @@ def test_static_camera_sequence_repeats_frame_zero(small_model):
         assert nm == 0 and mask.sum() == 0
         assert np.array_equal(rgb, rgb0.astype(np.float32).astype(np.float64))
         assert np.array_equal(dz, dz0.astype(np.float32).astype(np.float64))
+
+
+def test_upsample_matches_torch_and_affine():
+    import torch
+    import torch.nn.functional as F
+    rng = np.random.default_rng(6)
+    for (w, h, s) in ((5, 4, 2), (8, 8, 2), (7, 3, 3)):
+        img = rng.uniform(0, 1, (h * w, 3))
+        W, H = w * s, h * s
+        got = seq.upsample_bilinear(img, w, h, W, H, s)
+        t = torch.from_numpy(img.reshape(h, w, 3).transpose(2, 0, 1)[None].copy())
+        ref = F.interpolate(t, size=(H, W), mode="bilinear", align_corners=False)[0].numpy()
+        assert np.allclose(got.reshape(H, W, 3), ref.transpose(1, 2, 0), atol=1e-12)
+    # an affine image is reproduced exactly away from the clamped border
+    w, h, s = 9, 7, 2
+    jj, ii = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    img = (0.3 + 0.1 * ii - 0.05 * jj).reshape(-1, 1)
+    up = seq.upsample_bilinear(img, w, h, w * s, h * s, s).reshape(h * s, w * s)
+    J, I = np.meshgrid(np.arange(h * s), np.arange(w * s), indexing="ij")
+    x, y = (I + 0.5) / s - 0.5, (J + 0.5) / s - 0.5
+    inner = (x >= 0) & (x <= w - 1) & (y >= 0) & (y <= h - 1)
+    assert np.allclose(up[inner], (0.3 + 0.1 * x - 0.05 * y)[inner], atol=1e-12)
+    # factor 1 is the identity
+    assert np.array_equal(seq.upsample_bilinear(img, w, h, w, h, 1), img)
+
+
+def test_low_res_camera_covers_the_same_view():
+    """The low-resolution pixel centre k + 1/2 and the full-resolution pixel
+    centres it covers see the same ray direction on average: pixel (k) of the
+    small camera looks where pixels (s k .. s k + s - 1) look."""
+    W, H = 64, 48
+    f, cx, cy = synth.intrinsics(W, H)
+    w, h, fl, cxl, cyl = seq.low_res_camera(W, H, f, cx, cy, 2)
+    assert (w, h) == (32, 24)
+    k = np.arange(w)
+    a_low = (k + 0.5 - cxl) / fl
+    a_full = ((2 * k + 0.5 - cx) / f + (2 * k + 1.5 - cx) / f) / 2
+    assert np.allclose(a_low, a_full, atol=1e-6)
+    assert seq.low_res_camera(65, 49, f, cx, cy, 2)[:2] == (33, 25)
+
+
+def test_temporal_static_camera(small_model):
+    """Temp-N with a camera that does not move: every frame repeats the last
+    full render and nothing is re-rendered between full renders."""
+    W = H = 24
+    f = synth.intrinsics(W, H)[0]
+    pose = synth.as_f32(synth.orbit_pose(0)).reshape(3, 4)
+    op = oracle.opts(64, 1e-4)
+    frames = seq.render_temporal(small_model, op, W, H, f, W / 2, H / 2, [pose] * 7, window=3)
+    for k in range(7):
+        rgb, dz, mask, nm = frames[k]
+        if k % 3 == 0:
+            assert nm == W * H
+        else:
+            assert nm == 0
+            assert np.array_equal(rgb, frames[k - 1][0].astype(np.float32).astype(np.float64))
+
+
+def test_temporal_window_one_is_full_rendering(small_model):
+    W = H = 16
+    f = synth.intrinsics(W, H)[0]
+    poses = [synth.as_f32(synth.orbit_pose(k, step_deg=5.0)).reshape(3, 4) for k in range(3)]
+    op = oracle.opts(64, 1e-4)
+    frames = seq.render_temporal(small_model, op, W, H, f, W / 2, H / 2, poses, window=1)
+    for k in range(3):
+        rgb, _, _, _ = oracle.render_pixels(small_model, op, oracle.camera(W, H, f, W / 2, H / 2, poses[k].reshape(12)))
+        assert np.array_equal(frames[k][0], rgb)
