@@ -216,6 +216,43 @@ def sequence_bench(model, opts, W, H, n_frames=65, window=16):
     return res
 
 
+def variants_bench(model, opts, W, H, n_frames=32):
+    """The paper's comparison variants on the same 32-frame orbit as the
+    SpaRW sweep: DS-2 (half resolution + bilinear upsample) and Temp-N
+    (warp from the previous output frame, full render every N frames), with
+    PSNR against full renders of the same frames."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    cams = [camera(W, H, synth.orbit_pose(k)) for k in range(n_frames)]
+    full = [cic.render_frame(model, opts, c)[0] for c in cams]
+    torch.cuda.synchronize()
+    out = {}
+    for fac in (2,):
+        [cic.render_frame_ds(model, opts, cams[0], fac) for _ in range(2)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        imgs = [cic.render_frame_ds(model, opts, c, fac) for c in cams]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ps = [psnr(imgs[k], full[k]) for k in range(n_frames)]
+        out["ds%d" % fac] = {"fps": n_frames / (t1 - t0), "psnr_vs_full_mean_db": float(np.mean(ps)),
+                             "psnr_vs_full_min_db": float(np.min(ps))}
+    for win in (6, 16):
+        cic.render_temporal(model, opts, cams, win)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rgb, dz, mask, nm = cic.render_temporal(model, opts, cams, win)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ps = [psnr(rgb[k], full[k]) for k in range(n_frames) if k % win]
+        fr = [int(nm[k]) / float(W * H) for k in range(n_frames) if k % win]
+        out["temp%d" % win] = {"fps": n_frames / (t1 - t0), "psnr_vs_full_mean_db": float(np.mean(ps)),
+                               "psnr_vs_full_min_db": float(np.min(ps)), "mask_fraction_mean": float(np.mean(fr))}
+    return out
+
+
 def precision_bench(scene, occ, steps):
     """Eight 800x800 views on the radius-4 sphere in one render_rays call:
     FP16 grids + BF16 MLP against the FP32 path on the same rays."""
@@ -463,6 +500,9 @@ def main():
     if not args.skip_sparw:
         log("off-trajectory references, serial vs two streams")
         out["sequence"] = sequence_bench(model, opts, W, H)
+    if not args.skip_sparw:
+        log("comparison variants DS-2, Temp-6, Temp-16")
+        out["variants"] = variants_bench(model, opts, W, H)
     if not args.skip_precision:
         log("precision path (8 views, FP16 grid + BF16 MLP)")
         out["precision"] = precision_bench(scene, model.occupancy, max(3, args.steps // 4))

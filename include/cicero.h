@@ -71,7 +71,8 @@ enum {
     CIC_OP_WARP_FRAME = 2,
     CIC_OP_RENDER_FRAME_SPARW = 3,
     CIC_OP_RENDER_BACKWARD = 4,
-    CIC_OP_RENDER_SEQUENCE = 5      /* n_items = pixels per frame */
+    CIC_OP_RENDER_SEQUENCE = 5,     /* n_items = pixels per frame */
+    CIC_OP_RENDER_FRAME_DS = 6      /* n_items = full-resolution pixels */
 };
 
 typedef struct {
@@ -222,7 +223,7 @@ int cic_extrapolate_pose(const float c2w_prev[12], const float c2w_cur[12], floa
 int cic_relative_pose(const float c2w_ref[12], const float c2w_tgt[12], float ref_T_tgt[12]);
 
 /* render_sequence flags */
-enum { CIC_SEQ_OVERLAP = 1 };
+enum { CIC_SEQ_OVERLAP = 1, CIC_SEQ_TEMPORAL = 2 };
 
 /* A camera trajectory rendered with SpaRW and off-trajectory references
  * (Sec. III-C, Eq. 5-6; Fig. 7 and 8 for the pipelines).
@@ -255,13 +256,29 @@ enum { CIC_SEQ_OVERLAP = 1 };
  * n_eval as in render_rays.  ref_c2w (host, nullable) receives the poses of
  * R_1, R_2, ... ([n_windows - 1][12]).  Workspace:
  * cic_workspace_bytes(CIC_OP_RENDER_SEQUENCE, H*W, ...).  Calls that share
- * a device from several host threads at once are not supported. */
+ * a device from several host threads at once are not supported.
+ * flags = CIC_SEQ_TEMPORAL selects the Temp-N comparison variant of the
+ * paper's evaluation instead (Sec. VI-B): frames 0, N, 2N, ... are rendered
+ * in full and every other frame is warped from the previous output frame
+ * (its colour and z-depth, with its own pose), holes rendered, so warping
+ * errors carry from frame to frame; lead, target_cus_per_xcd and ref_c2w are
+ * unused and OVERLAP may not be combined with it. */
 int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
                     const cic_camera *cams, int32_t n_frames, int32_t window, float lead, int32_t flags,
                     int32_t target_cus_per_xcd,
                     float *rgb, float *depth_z, uint8_t *mask, int64_t *n_masked,
                     float *ref_c2w, int64_t *n_eval,
                     void *ws, size_t ws_bytes, cic_stream_t stream);
+
+/* DS-s comparison variant of the paper's evaluation (Sec. VI-B, DS-2):
+ * render the frame at 1/factor resolution -- same pose, ceil(W/s) x ceil(H/s)
+ * pixels, focal length f/s and principal point (cx/s, cy/s), in float32 --
+ * then upsample the colour bilinearly to W x H (output pixel centre i + 1/2
+ * at (i + 1/2)/s - 1/2 in low-resolution pixel index space, border clamped).
+ * factor in [1, 16]; rgb [H*W][3] device float32; n_eval as in render_rays.
+ * Workspace: cic_workspace_bytes(CIC_OP_RENDER_FRAME_DS, W*H, ...). */
+int render_frame_ds(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cam,
+                    int32_t factor, float *rgb, int64_t *n_eval, void *ws, size_t ws_bytes, cic_stream_t stream);
 
 /* Adjoint of render_rays (the derivative of the same quadrature; the paper
  * itself is inference-only).  The forward is recomputed per ray; nothing

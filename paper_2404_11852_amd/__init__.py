@@ -10,7 +10,8 @@ from ._lib import (CIC_F16, CIC_F32, CIC_BF16, CIC_ORDER_RAY, CIC_ORDER_VOXEL, C
                    make_camera, make_opts, relative_pose)
 
 __all__ = ["Model", "make_camera", "make_opts", "CicError", "render_rays", "render_frame", "warp_frame",
-           "render_frame_sparw", "render_sequence", "render_backward", "generate_rays", "build_occupancy",
+           "render_frame_sparw", "render_sequence", "render_temporal", "render_frame_ds", "render_backward",
+           "generate_rays", "build_occupancy",
            "extrapolate_pose", "relative_pose", "RenderRays",
            "CIC_F32", "CIC_F16", "CIC_BF16", "CIC_ORDER_RAY", "CIC_ORDER_VOXEL"]
 
@@ -118,6 +119,28 @@ def render_sequence(model, opts, cams, window, lead=-1.0, overlap=True, target_c
                                 _lib.CIC_SEQ_OVERLAP if overlap else 0, rgb, dz, mask, nm, n_eval,
                                 target_cus_per_xcd)
     return rgb, dz, mask, nm, refs
+
+
+def render_temporal(model, opts, cams, window, n_eval=None):
+    """Temp-N variant: full renders every `window` frames, every other frame
+    warped from the previous output.  Returns rgb, z-depth, mask, counts."""
+    n = len(cams)
+    npix = cams[0].width * cams[0].height
+    dev = model.device
+    rgb = torch.empty((n, npix, 3), dtype=torch.float32, device=dev)
+    dz = torch.empty((n, npix), dtype=torch.float32, device=dev)
+    mask = torch.empty((n, npix), dtype=torch.uint8, device=dev)
+    nm = torch.zeros(n, dtype=torch.int64, device=dev)
+    _lib.render_sequence(model.grid, model.mlp, opts, cams, window, 0.0, _lib.CIC_SEQ_TEMPORAL, rgb, dz, mask, nm,
+                         n_eval)
+    return rgb, dz, mask, nm
+
+
+def render_frame_ds(model, opts, cam, factor=2, n_eval=None):
+    """DS-s variant: render at 1/factor resolution, upsample bilinearly."""
+    rgb = _f32(cam.width * cam.height, 3, device=model.device)
+    _lib.render_frame_ds(model.grid, model.mlp, opts, cam, factor, rgb, n_eval)
+    return rgb
 
 
 def render_backward(model, opts, rays_o, rays_d, d_rgb, d_depth_t=None, d_acc=None, grads=None):

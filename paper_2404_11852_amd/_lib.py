@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libcicero.so")
 CIC_F32, CIC_F16, CIC_BF16 = 0, 1, 2
 CIC_ORDER_RAY, CIC_ORDER_VOXEL = 0, 1
 (OP_RENDER_RAYS, OP_RENDER_FRAME, OP_WARP_FRAME, OP_RENDER_FRAME_SPARW, OP_RENDER_BACKWARD,
- OP_RENDER_SEQUENCE) = range(6)
-CIC_SEQ_OVERLAP = 1
+ OP_RENDER_SEQUENCE, OP_RENDER_FRAME_DS) = range(7)
+CIC_SEQ_OVERLAP, CIC_SEQ_TEMPORAL = 1, 2
 
 
 class CicError(RuntimeError):
@@ -53,7 +53,8 @@ class Camera(C.Structure):
 
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
            "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
-           "cic_timing_read", "cic_extrapolate_pose", "cic_relative_pose", "render_sequence", "cic_timing_frames"]
+           "cic_timing_read", "cic_extrapolate_pose", "cic_relative_pose", "render_sequence", "cic_timing_frames",
+           "render_frame_ds"]
 STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad", "embed"]
 
 _lib = None
@@ -89,6 +90,7 @@ def lib():
                 L.render_sequence.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, f, C.c_int32, C.c_int32, vp,
                                               vp, vp, vp, vp, vp, vp, u64, vp]
                 L.cic_timing_frames.argtypes = [vp, C.c_int]
+                L.render_frame_ds.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, u64, vp]
                 for name in EXPORTS[2:]:
                     getattr(L, name).restype = C.c_int
                 _lib = L
@@ -299,3 +301,10 @@ def timing_frames(cap=4096):
     if n < 0:
         raise CicError(n, last_error())
     return list(ms[:min(n, cap)])
+
+
+def render_frame_ds(grid, mlp, opts, cam, factor, rgb, n_eval=None):
+    nb = workspace_bytes(OP_RENDER_FRAME_DS, cam.width * cam.height, grid, opts)
+    ws = workspace(nb, rgb.device)
+    _check(lib().render_frame_ds(C.byref(grid), C.byref(mlp), C.byref(opts), C.byref(cam), C.c_int32(factor),
+                                 _ptr(rgb), _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()), _stream()))

@@ -261,6 +261,14 @@ size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
     case CIC_OP_RENDER_SEQUENCE:
         carve_seq(cv, n, o, nb);
         break;
+    case CIC_OP_RENDER_FRAME_DS: {   // low-resolution colour and depth, then one render pass (bounded by n)
+        cv.take<float>(3 * n);
+        cv.take<float>(n);
+        cv.off = (cv.off + 255) & ~(size_t)255;
+        const int64_t nc = n < kChunkRays ? n : kChunkRays;
+        carve_render(cv, nc, o->n_samples, nb, voxel, true);
+        break;
+    }
     case CIC_OP_RENDER_BACKWARD: {
         const int64_t nc = n < kChunkRaysBwd ? n : kChunkRaysBwd;
         RenderBufs b = carve_render(cv, nc, o->n_samples, nb, false, false);
@@ -727,7 +735,10 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     if (n_frames == 0) return ok();
     if (window < 1) return fail(CIC_ERR_INVALID, "window must be >= 1");
     if (!finite_f(lead)) return fail(CIC_ERR_INVALID, "lead is not finite");
-    if ((flags & ~CIC_SEQ_OVERLAP) != 0) return fail(CIC_ERR_INVALID, "unknown flags 0x%x", flags);
+    if ((flags & ~(CIC_SEQ_OVERLAP | CIC_SEQ_TEMPORAL)) != 0) return fail(CIC_ERR_INVALID, "unknown flags 0x%x", flags);
+    const bool temporal = (flags & CIC_SEQ_TEMPORAL) != 0;
+    if (temporal && (flags & CIC_SEQ_OVERLAP))
+        return fail(CIC_ERR_INVALID, "CIC_SEQ_TEMPORAL cannot be combined with CIC_SEQ_OVERLAP");
     if (target_cus_per_xcd < 0 || (target_cus_per_xcd > 0 && !(flags & CIC_SEQ_OVERLAP)))
         return fail(CIC_ERR_INVALID, "target_cus_per_xcd needs CIC_SEQ_OVERLAP and must be >= 0");
     if (!cams) return fail(CIC_ERR_INVALID, "cams is NULL");
@@ -743,6 +754,37 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     const size_t need = bytes_for(CIC_OP_RENDER_SEQUENCE, np, grid, opts);
     if ((rc = check_ws(need, ws, ws_bytes))) return rc;
     if ((rc = check_device())) return rc;
+
+    if (temporal) {
+        // Temp-N: full renders every `window` frames, otherwise a warp from the previous output
+        hipStream_t s = (hipStream_t)stream;
+        const bool voxel = opts->order == CIC_ORDER_VOXEL;
+        const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+        const OptsK ok_ = make_optsk(opts);
+        Carver cv(align_ws(ws));
+        SeqBufs q = carve_seq(cv, np, opts, n_bricks_of(grid));
+        if (g_timing.on) {
+            g_timing.reset_frames();
+            g_timing.frame0 = g_timing.get();
+            if (g_timing.frame0) (void)hipEventRecord(g_timing.frame0, s);
+        }
+        for (int32_t k = 0; k < n_frames; ++k) {
+            float *o_rgb = rgb + 3 * np * k, *o_dz = depth_z + np * k;
+            if (k % window == 0) {
+                full_frame(grid, gk, mlp, ok_, voxel, q.a, cams[k], o_rgb, o_dz, n_eval, s);
+                launch_fill_u8(mask + np * k, 1, np, s);
+                if (n_masked) launch_fill_u64((uint64_t *)(n_masked + k), (uint64_t)np, 1, s);
+            } else {
+                float T[12];
+                if (cic_relative_pose(cams[k - 1].c2w, cams[k].c2w, T) != CIC_OK)
+                    return fail(CIC_ERR_INVALID, "relative pose failed for frame %d", k);
+                sparw_frame(grid, gk, mlp, opts, ok_, voxel, q.w, q.a, cams[k - 1], o_rgb - 3 * np, o_dz - np,
+                            cams[k], T, o_rgb, o_dz, mask + np * k, n_masked ? n_masked + k : nullptr, n_eval, s);
+            }
+            frame_mark(s);
+        }
+        return after_launch("render_sequence");
+    }
 
     // reference poses (host): R_0 = frame 0, R_{w+1} from the poses known when window w starts
     const int32_t n_win = (n_frames - 1 + window - 1) / window;
@@ -838,6 +880,49 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         }
     }
     return after_launch("render_sequence");
+}
+
+int render_frame_ds(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cam,
+                    int32_t factor, float *rgb, int64_t *n_eval, void *ws, size_t ws_bytes, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid)) ||
+        (rc = check_camera(cam, "")))
+        return rc;
+    if (factor < 1 || factor > 16) return fail(CIC_ERR_INVALID, "factor=%d outside [1,16]", factor);
+    if (!rgb) return fail(CIC_ERR_INVALID, "rgb is NULL");
+    const int64_t np = (int64_t)cam->width * cam->height;
+    const size_t need = bytes_for(CIC_OP_RENDER_FRAME_DS, np, grid, opts);
+    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    if ((rc = check_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    cic_camera lo = *cam;
+    lo.width = (cam->width + factor - 1) / factor;
+    lo.height = (cam->height + factor - 1) / factor;
+    lo.f = cam->f / (float)factor;
+    lo.cx = cam->cx / (float)factor;
+    lo.cy = cam->cy / (float)factor;
+    const int64_t nl = (int64_t)lo.width * lo.height;
+    const bool voxel = opts->order == CIC_ORDER_VOXEL;
+    const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
+    const OptsK ok_ = make_optsk(opts);
+    const int64_t nb = n_bricks_of(grid);
+    Carver c0(align_ws(ws));
+    float *lo_rgb = c0.take<float>(3 * np);
+    float *lo_dz = c0.take<float>(np);
+    const size_t render_off = (c0.off + 255) & ~(size_t)255;
+    for (int64_t r0 = 0; r0 < nl; r0 += kChunkRays) {
+        const int64_t nc = (nl - r0) < kChunkRays ? (nl - r0) : kChunkRays;
+        Carver cv((char *)align_ws(ws) + render_off);
+        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, true);
+        {
+            StageTimer t(CIC_STAGE_RAYGEN, s);
+            launch_generate_rays(lo, nc, r0, nullptr, nullptr, nullptr, (float *)b.rays_o, (float *)b.rays_d, s);
+        }
+        run_pipeline(grid, gk, mlp, ok_, voxel, b, lo_rgb + 3 * r0, lo_dz + r0, nullptr, nullptr, &lo, n_eval, s);
+    }
+    launch_upsample_bilinear(lo_rgb, lo.width, lo.height, rgb, cam->width, cam->height, factor, s);
+    return after_launch("render_frame_ds");
 }
 
 int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,

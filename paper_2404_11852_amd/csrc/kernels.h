@@ -63,6 +63,9 @@ void launch_brick_scatter(const RenderBufs &b, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+
+// upsample.hip
+void launch_upsample_bilinear(const float *lo, int w, int h, float *out, int W, int H, int s, hipStream_t st);
 // Final per-ray accumulation.  out_map (nullable) maps ray -> output slot;
 // frame_cam (nullable) switches depth output to frame z-depth.
 void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,
