@@ -28,11 +28,17 @@ def build(force=True):
     return _LIB
 
 
+class Hash(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("feat_per_level", C.c_int32), ("res", C.c_int32 * 8),
+                ("log2_size", C.c_int32), ("tables", C.c_void_p)]
+
+
 class Grid(C.Structure):
     _fields_ = [("res", C.c_int32 * 3), ("n_feat", C.c_int32),
                 ("box_lo", C.c_float * 3), ("box_hi", C.c_float * 3),
                 ("density_shift", C.c_float),
-                ("density", C.c_void_p), ("features", C.c_void_p), ("occ", C.c_void_p)]
+                ("density", C.c_void_p), ("features", C.c_void_p), ("occ", C.c_void_p),
+                ("hash", C.c_void_p)]
 
 
 class MLP(C.Structure):
@@ -75,16 +81,30 @@ class Model:
     """Holds contiguous arrays plus the ctypes structs that point at them."""
 
     def __init__(self, density, features, mlp, box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3,
-                 density_shift=0.0, occ=None, pe_freqs=4, round_bf16=False):
+                 density_shift=0.0, occ=None, pe_freqs=4, round_bf16=False, hash_enc=None):
+        """hash_enc: None (features from the dense grid `features`) or a dict
+        with 'res' (cells per axis of each level), 'log2_size' and 'tables'
+        [L][2^log2_size][F]; then `features` is ignored."""
         self.density = _f32(density)
-        self.features = _f32(features)
         res = self.density.shape
-        n_feat = self.features.shape[-1]
+        self.hash = None
+        if hash_enc is not None:
+            self.tables = _f32(hash_enc["tables"])
+            L, T, F = self.tables.shape
+            assert T == 1 << int(hash_enc["log2_size"]) and L == len(hash_enc["res"]) <= 8
+            self.hash = Hash(L, F, (C.c_int32 * 8)(*hash_enc["res"]), int(hash_enc["log2_size"]),
+                             _p(self.tables).value)
+            self.features = np.zeros((1,), np.float32)
+            n_feat = L * F
+        else:
+            self.features = _f32(features)
+            n_feat = self.features.shape[-1]
         self.occ = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
         self.grid = Grid((C.c_int32 * 3)(*res), n_feat, (C.c_float * 3)(*box_lo),
                          (C.c_float * 3)(*box_hi), float(np.float32(density_shift)),
                          _p(self.density).value, _p(self.features).value,
-                         None if self.occ is None else _p(self.occ).value)
+                         None if self.occ is None else _p(self.occ).value,
+                         None if self.hash is None else C.addressof(self.hash))
         self.w = {k: _f32(v) for k, v in mlp.items()}
         hidden, in_dim = self.w["w0"].shape
         out_dim = self.w["w2"].shape[0]
@@ -260,3 +280,12 @@ def render_backward(model, op, o, d, d_rgb, d_depth_t=None, d_acc=None):
                               _p(g["w0"]), _p(g["b0"]), _p(g["w1"]), _p(g["b1"]),
                               _p(g["w2"]), _p(g["b2"]), _p(rgb), _p(dep), _p(acc))
     return g, (rgb, dep, acc)
+
+
+def encode(model, pos):
+    """Feature vectors [n][n_feat] (float64) of float32 positions [n][3]:
+    the multi-level encoding when the model has one, else the dense grid."""
+    pos = _f32(pos).reshape(-1, 3)
+    out = np.empty((pos.shape[0], model.grid.n_feat), np.float64)
+    lib().orc_encode(C.byref(model.grid), C.c_int64(pos.shape[0]), _p(pos), _p(out))
+    return out

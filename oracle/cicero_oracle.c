@@ -46,6 +46,21 @@
 #include <omp.h>
 #endif
 
+/* Multi-level feature encoding (the hierarchical encodings of Sec. IV-A's
+ * last paragraph, in the form of a multiresolution hash grid): level l has
+ * res[l] cells per axis over the box; its vertex (x, y, z) is entry
+ * (x (N+1) + y)(N+1) + z of the level's table when (N+1)^3 fits the table,
+ * else the spatial hash (x * 1 ^ y * 2654435761 ^ z * 805459861) mod T in
+ * 32-bit unsigned arithmetic (T a power of two).  The feature vector is the
+ * levels' trilinearly interpolated entries, level-major. */
+typedef struct {
+    int32_t levels;          /* L */
+    int32_t feat_per_level;  /* F; L * F = n_feat */
+    int32_t res[8];          /* cells per axis of each level */
+    int32_t log2_size;       /* T = 2^log2_size entries per level */
+    const float *tables;     /* [L][T][F] */
+} orc_hash;
+
 typedef struct {
     int32_t res[3];          /* vertices per axis */
     int32_t n_feat;          /* feature channels per vertex */
@@ -53,8 +68,9 @@ typedef struct {
     float box_hi[3];
     float density_shift;     /* added to the interpolated raw density before softplus */
     const float *density;    /* raw density [r0][r1][r2], z fastest */
-    const float *features;   /* [r0][r1][r2][n_feat], channel fastest */
+    const float *features;   /* [r0][r1][r2][n_feat], channel fastest (unused with hash) */
     const uint8_t *occ;      /* [(r0-1)(r1-1)(r2-1)] cell flags, or NULL */
+    const orc_hash *hash;    /* NULL: features from the dense grid */
 } orc_grid;
 
 typedef struct {
@@ -174,6 +190,73 @@ static void corner_indices(const orc_grid *g, const int i0[3], int64_t idx[8])
     for (int v = 0; v < 8; ++v) {
         int dx = (v >> 2) & 1, dy = (v >> 1) & 1, dz = v & 1;
         idx[v] = vertex_index(g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+    }
+}
+
+/* One level of the multi-level encoding at position x (float32 locate,
+ * float64 interpolation); adds nothing else. */
+static void hash_level(const orc_hash *h, int l, const float lo[3], const float hi[3], const float x[3],
+                       double *out)
+{
+    const int N = h->res[l], F = h->feat_per_level;
+    const uint32_t T = 1u << h->log2_size;
+    const int dense = (int64_t)(N + 1) * (N + 1) * (N + 1) <= (int64_t)T;
+    int i0[3];
+    float fr[3];
+    for (int a = 0; a < 3; ++a) {
+        float scale = (float)N / (hi[a] - lo[a]);
+        float u = (x[a] - lo[a]) * scale;
+        int i = (int)floorf(u);
+        if (i < 0) i = 0;
+        if (i > N - 1) i = N - 1;
+        float f = u - (float)i;
+        fr[a] = fminf(fmaxf(f, 0.0f), 1.0f);
+        i0[a] = i;
+    }
+    double w[8];
+    trilinear_weights(fr, w);
+    const float *tab = h->tables + (size_t)l * T * F;
+    for (int f = 0; f < F; ++f) out[f] = 0.0;
+    for (int v = 0; v < 8; ++v) {
+        uint32_t vx = (uint32_t)(i0[0] + ((v >> 2) & 1)), vy = (uint32_t)(i0[1] + ((v >> 1) & 1)),
+                 vz = (uint32_t)(i0[2] + (v & 1));
+        uint32_t e = dense ? (vx * (uint32_t)(N + 1) + vy) * (uint32_t)(N + 1) + vz
+                           : ((vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u)) & (T - 1u);
+        for (int f = 0; f < F; ++f) out[f] += w[v] * (double)tab[(size_t)e * F + f];
+    }
+}
+
+/* Feature vector of a sample: the dense grid's trilinear interpolation, or
+ * the multi-level encoding's levels in order. */
+static void sample_features(const orc_grid *g, const float x[3], const double wv[8], const int64_t idx[8],
+                            double *feat)
+{
+    if (g->hash) {
+        for (int l = 0; l < g->hash->levels; ++l)
+            hash_level(g->hash, l, g->box_lo, g->box_hi, x, feat + l * g->hash->feat_per_level);
+        return;
+    }
+    const int C = g->n_feat;
+    for (int ch = 0; ch < C; ++ch) {
+        double s = 0.0;
+        for (int v = 0; v < 8; ++v) s += wv[v] * (double)g->features[idx[v] * C + ch];
+        feat[ch] = s;
+    }
+}
+
+/* Encode n positions [n][3] with the grid's multi-level encoding (or dense
+ * features): out [n][n_feat]. */
+void orc_encode(const orc_grid *g, int64_t n, const float *pos, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int i0[3];
+        float fr[3];
+        double wv[8];
+        int64_t idx[8];
+        locate_f32(g, pos + 3 * i, i0, fr);
+        trilinear_weights(fr, wv);
+        corner_indices(g, i0, idx);
+        sample_features(g, pos + 3 * i, wv, idx, out + i * g->n_feat);
     }
 }
 
@@ -317,11 +400,7 @@ static void render_ray(const orc_grid *g, const orc_mlp *m, const orc_opts *op,
         double att = exp(-sigma * (double)delta);
         double alpha = 1.0 - att;
         double w = T * alpha;
-        for (int ch = 0; ch < C; ++ch) {
-            double s = 0.0;
-            for (int v = 0; v < 8; ++v) s += wv[v] * (double)g->features[idx[v] * C + ch];
-            feat[ch] = s;
-        }
+        sample_features(g, xp, wv, idx, feat);
         mlp_input(m, C, feat, d, x);
         mlp_forward(m, x, h1, h2, c);
         for (int u = 0; u < H; ++u) {
@@ -708,6 +787,7 @@ void orc_render_backward(const orc_grid *g, const orc_mlp *m, const orc_opts *op
                          double *d_w2, double *d_b2,
                          double *rgb_out, double *depth_out, double *acc_out)
 {
+    if (g->hash) return;   /* the adjoint is defined for the dense feature grid only */
     int N = op->n_samples, C = g->n_feat;
     int I = m->in_dim, H = m->hidden, O = m->out_dim;
     int64_t nw0 = (int64_t)H * I, nw1 = (int64_t)H * H, nw2 = (int64_t)O * H;

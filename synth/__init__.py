@@ -11,8 +11,8 @@ dense voxel-grid model, camera orbits with small per-frame motion) with
 synthetic content standing in for the trained models and datasets, which are
 not available here.
 """
-from .scene import (BOX_LO, BOX_HI, DENSITY_SHIFT, OCC_SIGMA, N_FEAT,
-                    make_scene, make_mlp, make_model_grid)
+from .scene import (BOX_LO, BOX_HI, DENSITY_SHIFT, OCC_SIGMA, N_FEAT, HASH_RES, HASH_LOG2_SIZE, HASH_FEAT,
+                    make_scene, make_mlp, make_model_grid, make_hash_tables)
 from .camera import (intrinsics, look_at, orbit_pose, orbit_poses,
                      sphere_poses, relative_pose, Camera, make_camera, as_f32)
 from .rays import random_rays, pixel_subset, training_pixels
@@ -20,6 +20,7 @@ from .configs import CONFIGS, get_config
 
 __all__ = [
     "BOX_LO", "BOX_HI", "DENSITY_SHIFT", "OCC_SIGMA", "N_FEAT",
+    "HASH_RES", "HASH_LOG2_SIZE", "HASH_FEAT", "make_hash_tables",
     "make_scene", "make_mlp", "make_model_grid",
     "intrinsics", "look_at", "orbit_pose", "orbit_poses", "sphere_poses",
     "relative_pose", "Camera", "make_camera", "as_f32",

@@ -99,3 +99,18 @@ def make_mlp(seed=1, in_dim=N_FEAT + 27, hidden=128, out_dim=3, bias_std=0.0):
             bs.append(np.zeros(fo, dtype=np.float32))
     return {"w0": ws[0], "b0": bs[0], "w1": ws[1], "b1": bs[1],
             "w2": ws[2], "b2": bs[2]}
+
+
+# multi-level (hash-grid) encoding: 4 levels x 3 features = the 12 MLP inputs
+HASH_RES = (32, 64, 128, 256)
+HASH_LOG2_SIZE = 19
+HASH_FEAT = 3
+
+
+def make_hash_tables(seed=30, res=HASH_RES, log2_size=HASH_LOG2_SIZE, feat=HASH_FEAT, std=0.2):
+    """Feature tables [L][2^log2_size][F] of a multi-level encoding, entries
+    drawn N(0, std) in float64 and stored float32 (every entry drawn, also
+    the ones a dense level leaves unused)."""
+    rng = np.random.default_rng(seed)
+    t = rng.normal(0.0, std, (len(res), 1 << log2_size, feat))
+    return {"res": tuple(int(r) for r in res), "log2_size": int(log2_size), "tables": t.astype(np.float32)}
