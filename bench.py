@@ -253,6 +253,29 @@ def variants_bench(model, opts, W, H, n_frames=32):
     return out
 
 
+def hash_bench(W, H, steps, dense_ms=None):
+    """The multi-level encoding workload (hierarchical encodings): the same
+    160^3 density grid and MLP, features from 4 levels of 3 features (32, 64,
+    128, 256 cells per axis; 2^19-entry tables, the two finest levels
+    hashed), 800x800 frames in ray and voxel order."""
+    import synth
+    import paper_2404_11852_amd as cic
+    dens, _ = synth.make_scene(160, seed=0)
+    h = synth.make_hash_tables(30)
+    model = cic.Model(dens, None, synth.make_mlp(1), density_shift=synth.DENSITY_SHIFT, hash_enc=h)
+    model.build_occupancy(synth.OCC_SIGMA)
+    cam = camera(W, H, synth.orbit_pose(0))
+    out = {"levels_cells": list(h["res"]), "log2_table": h["log2_size"],
+           "hashed_levels": [int((r + 1) ** 3 > (1 << h["log2_size"])) for r in h["res"]]}
+    for name, order in (("ray", cic.CIC_ORDER_RAY), ("voxel", cic.CIC_ORDER_VOXEL)):
+        opts = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=order)
+        t, n_eval, stages = timed_frames(model, opts, cam, steps, 2)
+        ms = 1e3 * t / steps
+        out[name] = {"ms_per_frame": ms, "samples_per_s": n_eval / t,
+                     "stage_ms": {k: v[0] / max(v[1], 1) * (v[1] / steps) for k, v in stages.items() if v[1]}}
+    return out
+
+
 def precision_bench(scene, occ, steps):
     """Eight 800x800 views on the radius-4 sphere in one render_rays call:
     FP16 grids + BF16 MLP against the FP32 path on the same rays."""
@@ -494,6 +517,8 @@ def main():
                      "flop_per_launch": MLP_FLOP_PER_SAMPLE * samples_per_frame,
                      "ms_per_launch": mlp_ms_per},
     }
+    log("multi-level encoding workload")
+    out["hash_encoding"] = hash_bench(W, H, max(3, args.steps // 4))
     if not args.skip_sparw:
         log("SpaRW orbit")
         out["sparw"] = sparw_sweep(model, opts, W, H)

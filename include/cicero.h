@@ -85,6 +85,20 @@ typedef struct {
     const void *density;       /* device, [res0][res1][res2] */
     const void *features;      /* device, [res0][res1][res2][n_feat] */
     const uint8_t *occupancy;  /* device, [(res0-1)(res1-1)(res2-1)], or NULL */
+    /* Multi-level feature encoding (the hierarchical encodings of Sec. IV-A,
+     * as a multiresolution hash grid).  hash_levels = 0: the features come
+     * from `features`.  hash_levels = 4: `features` is unused and each
+     * sample's 12 features are 3 per level, level l interpolated trilinearly
+     * on a grid of hash_res[l] cells per axis over the box; vertex (x, y, z)
+     * of level l reads entry (x (N+1) + y)(N+1) + z of the level's table when
+     * (N+1)^3 <= 2^hash_log2_size, else entry
+     * (x * 1 ^ y * 2654435761 ^ z * 805459861) mod 2^hash_log2_size (32-bit
+     * unsigned arithmetic).  Density, occupancy and voxel order still use the
+     * dense density grid.  Forward rendering only (render_backward rejects it). */
+    int32_t hash_levels;       /* 0 or 4 */
+    int32_t hash_res[4];       /* cells per axis of each level, each in [1, 4096] */
+    int32_t hash_log2_size;    /* table entries per level = 2^hash_log2_size, in [8, 24] */
+    const void *hash_tables;   /* device, [4][2^hash_log2_size][3], of type `storage` */
 } cic_grid;
 
 typedef struct {

@@ -21,10 +21,20 @@ class Model:
     the 39-128-128-3 MLP, plus the C structs that describe them."""
 
     def __init__(self, density, features, mlp, device="cuda", storage=torch.float32, density_shift=0.0,
-                 box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3, compute=CIC_F32):
+                 box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3, compute=CIC_F32, hash_enc=None):
+        """hash_enc: None, or {'res': 4 level resolutions, 'log2_size': int,
+        'tables': [4][2^log2_size][3]} for the multi-level encoding (then
+        `features` is ignored)."""
         self.device = torch.device(device)
         self.density = torch.as_tensor(density, dtype=torch.float32).to(self.device).to(storage).contiguous()
-        self.features = torch.as_tensor(features, dtype=torch.float32).to(self.device).to(storage).contiguous()
+        self.hash = None
+        if hash_enc is not None:
+            self.hash = dict(hash_enc)
+            self.hash["tables"] = torch.as_tensor(hash_enc["tables"], dtype=torch.float32).to(self.device) \
+                .to(storage).contiguous()
+            self.features = None
+        else:
+            self.features = torch.as_tensor(features, dtype=torch.float32).to(self.device).to(storage).contiguous()
         self.w = {k: torch.as_tensor(v, dtype=torch.float32).to(self.device).contiguous() for k, v in mlp.items()}
         self.box_lo, self.box_hi = tuple(box_lo), tuple(box_hi)
         self.density_shift = float(density_shift)
@@ -33,8 +43,9 @@ class Model:
         self._rebuild()
 
     def _rebuild(self):
+        h = self.hash or {}
         self.grid = _lib.make_grid(self.density, self.features, self.occupancy, self.box_lo, self.box_hi,
-                                   self.density_shift)
+                                   self.density_shift, h.get("res"), h.get("log2_size", 0), h.get("tables"))
         self.mlp = _lib.make_mlp(self.w, self.compute)
 
     def build_occupancy(self, occ_sigma=1e-2):
@@ -145,7 +156,9 @@ def render_frame_ds(model, opts, cam, factor=2, n_eval=None):
 
 def render_backward(model, opts, rays_o, rays_d, d_rgb, d_depth_t=None, d_acc=None, grads=None):
     """Accumulate gradients of the rendering into `grads` (created zeroed if
-    None); returns the dict."""
+    None); returns the dict.  Dense feature grids only."""
+    if model.hash is not None:
+        raise CicError(-1, "render_backward does not support the multi-level encoding")
     if grads is None:
         grads = {"density": torch.zeros(model.density.shape, dtype=torch.float32, device=model.device),
                  "features": torch.zeros(model.features.shape, dtype=torch.float32, device=model.device)}

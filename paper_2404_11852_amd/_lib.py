@@ -31,7 +31,9 @@ class CicError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("res", C.c_int32 * 3), ("n_feat", C.c_int32), ("storage", C.c_int32),
                 ("box_lo", C.c_float * 3), ("box_hi", C.c_float * 3), ("density_shift", C.c_float),
-                ("density", C.c_void_p), ("features", C.c_void_p), ("occupancy", C.c_void_p)]
+                ("density", C.c_void_p), ("features", C.c_void_p), ("occupancy", C.c_void_p),
+                ("hash_levels", C.c_int32), ("hash_res", C.c_int32 * 4), ("hash_log2_size", C.c_int32),
+                ("hash_tables", C.c_void_p)]
 
 
 class MLP(C.Structure):
@@ -138,19 +140,27 @@ def free_workspace():
 # ---------------------------------------------------------------------------
 # struct builders
 # ---------------------------------------------------------------------------
-def make_grid(density, features, occupancy=None, box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3, density_shift=0.0):
-    if density.dtype == torch.float32 and features.dtype == torch.float32:
+def make_grid(density, features, occupancy=None, box_lo=(-1.5,) * 3, box_hi=(1.5,) * 3, density_shift=0.0,
+              hash_res=None, hash_log2_size=0, hash_tables=None):
+    """features: dense feature grid, or None with hash_tables [4][2^log2][3]
+    (the multi-level encoding); every grid tensor float32 or every float16."""
+    dense = hash_tables if features is None else features
+    if density.dtype == torch.float32 and dense.dtype == torch.float32:
         storage = CIC_F32
-    elif density.dtype == torch.float16 and features.dtype == torch.float16:
+    elif density.dtype == torch.float16 and dense.dtype == torch.float16:
         storage = CIC_F16
     else:
-        raise CicError(-1, "density/features must both be float32 or both float16")
-    if not (density.is_contiguous() and features.is_contiguous()):
+        raise CicError(-1, "grid tensors must all be float32 or all float16")
+    if not (density.is_contiguous() and dense.is_contiguous()):
         raise CicError(-1, "grids must be contiguous")
-    g = Grid((C.c_int32 * 3)(*density.shape), int(features.shape[-1]), storage, (C.c_float * 3)(*box_lo),
-             (C.c_float * 3)(*box_hi), float(density_shift), density.data_ptr(), features.data_ptr(),
-             occupancy.data_ptr() if occupancy is not None else None)
-    g._keep = (density, features, occupancy)
+    levels = 0 if features is not None else int(hash_tables.shape[0])
+    g = Grid((C.c_int32 * 3)(*density.shape), 12 if features is None else int(features.shape[-1]), storage,
+             (C.c_float * 3)(*box_lo), (C.c_float * 3)(*box_hi), float(density_shift), density.data_ptr(),
+             None if features is None else features.data_ptr(),
+             occupancy.data_ptr() if occupancy is not None else None,
+             levels, (C.c_int32 * 4)(*(hash_res or (0, 0, 0, 0))), int(hash_log2_size),
+             None if hash_tables is None else hash_tables.data_ptr())
+    g._keep = (density, features, occupancy, hash_tables)
     return g
 
 

@@ -69,7 +69,18 @@ int check_grid(const cic_grid *g)
     if (g->storage != CIC_F32 && g->storage != CIC_F16)
         return fail(CIC_ERR_INVALID, "grid.storage=%d; must be CIC_F32 or CIC_F16", g->storage);
     if (!finite_f(g->density_shift)) return fail(CIC_ERR_INVALID, "grid.density_shift is not finite");
-    if (!g->density || !g->features) return fail(CIC_ERR_INVALID, "grid.density/features is NULL");
+    if (!g->density) return fail(CIC_ERR_INVALID, "grid.density is NULL");
+    if (g->hash_levels == 0) {
+        if (!g->features) return fail(CIC_ERR_INVALID, "grid.features is NULL");
+    } else {
+        if (g->hash_levels != 4) return fail(CIC_ERR_INVALID, "grid.hash_levels=%d; must be 0 or 4", g->hash_levels);
+        for (int l = 0; l < 4; ++l)
+            if (g->hash_res[l] < 1 || g->hash_res[l] > 4096)
+                return fail(CIC_ERR_INVALID, "grid.hash_res[%d]=%d outside [1,4096]", l, g->hash_res[l]);
+        if (g->hash_log2_size < 8 || g->hash_log2_size > 24)
+            return fail(CIC_ERR_INVALID, "grid.hash_log2_size=%d outside [8,24]", g->hash_log2_size);
+        if (!g->hash_tables) return fail(CIC_ERR_INVALID, "grid.hash_tables is NULL");
+    }
     return CIC_OK;
 }
 
@@ -140,6 +151,18 @@ GridK make_gridk(const cic_grid *g, bool use_occ)
     k.occ = use_occ ? g->occupancy : nullptr;
     k.nb1 = (g->res[1] - 1 + kBrick - 1) / kBrick;
     k.nb2 = (g->res[2] - 1 + kBrick - 1) / kBrick;
+    k.hlevels = g->hash_levels;
+    if (g->hash_levels) {
+        const int64_t T = (int64_t)1 << g->hash_log2_size;
+        k.hmask = (uint32_t)(T - 1);
+        k.htab = g->hash_tables;
+        for (int l = 0; l < 4; ++l) {
+            const int64_t n1 = (int64_t)g->hash_res[l] + 1;
+            k.hN[l] = g->hash_res[l];
+            k.hdense[l] = n1 * n1 * n1 <= T ? 1 : 0;
+            for (int a = 0; a < 3; ++a) k.hscale[l][a] = (float)g->hash_res[l] / (g->box_hi[a] - g->box_lo[a]);
+        }
+    }
     return k;
 }
 
@@ -933,6 +956,7 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
     if (grid->storage != CIC_F32) return fail(CIC_ERR_INVALID, "render_backward needs a float32 grid");
+    if (grid->hash_levels) return fail(CIC_ERR_INVALID, "render_backward does not support the multi-level encoding");
     if (mlp->compute != CIC_F32) return fail(CIC_ERR_INVALID, "render_backward needs CIC_F32 compute");
     if (n_rays < 0) return fail(CIC_ERR_INVALID, "n_rays < 0");
     if (n_rays == 0) return ok();

@@ -31,6 +31,13 @@ struct GridK {
     const void *features;
     const uint8_t *occ;    // nullptr when skipping is off
     int nb1, nb2;          // bricks along axes 1 and 2
+    // multi-level encoding (hlevels = 0: dense features)
+    int hlevels;
+    int hN[4];             // cells per axis of each level
+    int hdense[4];         // level stored densely ((N+1)^3 fits the table)
+    float hscale[4][3];    // N / (hi - lo) per axis, float32 as computed on the host
+    uint32_t hmask;        // table entries per level - 1
+    const void *htab;      // [4][hmask+1][3]
 };
 
 struct OptsK {
@@ -154,6 +161,44 @@ __device__ __forceinline__ float trilerp1(const T *v, const GridK &g, const int 
     float c10 = lerpf(v100, v101, fr[2]), c11 = lerpf(v110, v111, fr[2]);
     float c0 = lerpf(c00, c01, fr[1]), c1 = lerpf(c10, c11, fr[1]);
     return lerpf(c0, c1, fr[0]);
+}
+
+// One level of the multi-level encoding at position x: 3 features,
+// trilinear over the level's cell (float32 locate, as the dense grid's).
+template <typename T>
+__device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x[3], float out[3])
+{
+    const int N = g.hN[l];
+    int i0[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = (x[a] - g.lo[a]) * g.hscale[l][a];
+        int i = (int)floorf(u);
+        i = i < 0 ? 0 : i;
+        i = i > N - 1 ? N - 1 : i;
+        const float f = u - (float)i;
+        fr[a] = fminf(fmaxf(f, 0.0f), 1.0f);
+        i0[a] = i;
+    }
+    const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
+    const uint32_t n1 = (uint32_t)N + 1u;
+    float v[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t vx = (uint32_t)(i0[0] + ((c >> 2) & 1)), vy = (uint32_t)(i0[1] + ((c >> 1) & 1)),
+                       vz = (uint32_t)(i0[2] + (c & 1));
+        const uint32_t e = g.hdense[l] ? (vx * n1 + vy) * n1 + vz
+                                       : (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & g.hmask;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) v[c][f] = ldv(tab, (int64_t)e * 3 + f);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const float c00 = lerpf(v[0][f], v[1][f], fr[2]), c01 = lerpf(v[2][f], v[3][f], fr[2]);
+        const float c10 = lerpf(v[4][f], v[5][f], fr[2]), c11 = lerpf(v[6][f], v[7][f], fr[2]);
+        out[f] = lerpf(lerpf(c00, c01, fr[1]), lerpf(c10, c11, fr[1]), fr[0]);
+    }
 }
 
 __device__ __forceinline__ float softplusf(float x)

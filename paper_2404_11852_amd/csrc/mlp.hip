@@ -101,12 +101,21 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
         o[a] = b.rays_o[3 * (int64_t)ray + a];
         d[a] = b.rays_d[3 * (int64_t)ray + a];
     }
-    int i0[3];
-    float fr[3], tk;
-    sample_voxel(o, d, inf.tn, inf.delta, k, g, i0, fr, tk);
-    const T *feat = (const T *)g.features;
+    if (g.hlevels) {
+        // multi-level encoding: lane group q gathers level q
+        const float tk = sample_t(inf.tn, inf.delta, k);
+        float xp[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+        for (int a = 0; a < 3; ++a) xp[a] = o[a] + tk * d[a];
+        hash_level3<T>(g, q, xp, x);
+    } else {
+        int i0[3];
+        float fr[3], tk;
+        sample_voxel(o, d, inf.tn, inf.delta, k, g, i0, fr, tk);
+        const T *feat = (const T *)g.features;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+    }
     if (!PE) {
 #pragma unroll
         for (int c = 3; c < 10; ++c) x[c] = 0.f;

@@ -49,6 +49,22 @@ def _good(L):
     return g, m, o
 
 
+def test_hash_grid_validation(L):
+    g, m, o = _good(L)
+    g.features = None
+    assert _render(L, g, m, o) == -1 and "features" in L.last_error()
+    g.hash_levels = 3
+    assert _render(L, g, m, o) == -1 and "hash_levels" in L.last_error()
+    g.hash_levels = 4
+    g.hash_res = (C.c_int32 * 4)(32, 64, 128, 0)
+    assert _render(L, g, m, o) == -1 and "hash_res" in L.last_error()
+    g.hash_res = (C.c_int32 * 4)(32, 64, 128, 256)
+    g.hash_log2_size = 30
+    assert _render(L, g, m, o) == -1 and "hash_log2_size" in L.last_error()
+    g.hash_log2_size = 19
+    assert _render(L, g, m, o) == -1 and "hash_tables" in L.last_error()
+
+
 def _render(L, g, m, o, n=16, ws=0x9000, ws_bytes=None):
     lib = L.lib()
     if ws_bytes is None:

@@ -1,0 +1,102 @@
+"""GPU parity of the multi-level (hash-grid) encoding path (hierarchical
+encodings, Sec. IV-A): rendering with the encoding against the oracle, in
+ray and voxel order, float32 and float16 tables, all-hashed small tables,
+and an 800x800 frame on sampled pixels."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import cams, compare, print_case, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+class HashPair:
+    def __init__(self, res=160, seed=0, mlp_seed=1, hres=synth.HASH_RES, log2_size=synth.HASH_LOG2_SIZE,
+                 hseed=30, storage=torch.float32, occupancy=True, compute=None):
+        import paper_2404_11852_amd as cic
+        dens, _ = synth.make_scene(res, seed=seed)
+        h = synth.make_hash_tables(hseed, res=hres, log2_size=log2_size)
+        mlp = synth.make_mlp(mlp_seed)
+        kw = {} if compute is None else {"compute": compute}
+        self.gpu = cic.Model(dens, None, mlp, storage=storage, density_shift=synth.DENSITY_SHIFT, hash_enc=h, **kw)
+        if storage == torch.float16:
+            dens = dens.astype(np.float16).astype(np.float32)
+            h = dict(h, tables=h["tables"].astype(np.float16).astype(np.float32))
+        self.orc = oracle.Model(dens, None, mlp, density_shift=synth.DENSITY_SHIFT, hash_enc=h,
+                                round_bf16=compute is not None)
+        if occupancy:
+            self.gpu.build_occupancy(synth.OCC_SIGMA)
+            self.orc.set_occupancy(oracle.build_occupancy(self.orc, synth.OCC_SIGMA))
+
+
+def _rays_check(p, n=4000, order=None, et=1e-4):
+    import paper_2404_11852_amd as cic
+    o, d = synth.random_rays(n, seed=8)
+    kw = {} if order is None else {"order": order}
+    go = cic.make_opts(256, et, True, **kw)
+    rgb, dep, acc = cic.render_rays(p.gpu, go, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    orgb, odep, oacc, diag = oracle.render_rays(p.orc, oracle.opts(256, et, True), o, d, diagnostics=True)
+    e1, nf = compare(to_np(rgb), orgb, margin=diag["margin"])
+    compare(to_np(dep), odep, margin=diag["margin"], what="depth_t")
+    compare(to_np(acc), oacc, margin=diag["margin"], what="acc")
+    print("max err %.2e, flagged %d" % (e1, nf))
+    return rgb, dep, acc
+
+
+@pytest.mark.parametrize("storage", [torch.float32, torch.float16])
+def test_hash_render_rays_matches_oracle(storage):
+    import paper_2404_11852_amd as cic
+    print_case("hash render_rays %s" % storage)
+    p = HashPair(storage=storage)
+    a = _rays_check(p)
+    b = _rays_check(p, order=cic.CIC_ORDER_VOXEL)
+    assert torch.equal(a[2], b[2]) and torch.equal(a[1], b[1])
+    assert float((a[0] - b[0]).abs().max()) <= 2e-6
+
+
+def test_hash_all_levels_hashed_small_table():
+    print_case("hash render_rays, 2^12 tables")
+    p = HashPair(res=64, hres=(24, 48, 96, 192), log2_size=12, hseed=31)
+    _rays_check(p, n=2000)
+
+
+def test_hash_frame_800_sampled():
+    import paper_2404_11852_amd as cic
+    print_case("hash frame 800x800")
+    W = H = 800
+    p = HashPair()
+    pose = synth.orbit_pose(4)
+    gc, oc = cams(W, H, pose)
+    go = cic.make_opts(256, 1e-4, True)
+    n_eval = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rgb, dz, acc = cic.render_frame(p.gpu, go, gc, n_eval=n_eval)
+    pix = synth.pixel_subset(W, H, 1500, seed=9)
+    orgb, odz, oacc, diag = oracle.render_pixels(p.orc, oracle.opts(256, 1e-4, True), oc, pix)
+    compare(to_np(rgb)[pix], orgb, margin=diag["margin"])
+    compare(to_np(acc)[pix], oacc, margin=diag["margin"], what="acc")
+    assert int(n_eval.item()) > 10_000_000
+
+
+def test_hash_bf16_against_bf16_oracle():
+    import paper_2404_11852_amd as cic
+    print_case("hash BF16 render_rays")
+    p = HashPair(compute=cic.CIC_BF16)
+    o, d = synth.random_rays(3000, seed=10)
+    go = cic.make_opts(256, 0.0, True)
+    rgb, _, _ = cic.render_rays(p.gpu, go, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    orgb, _, _ = oracle.render_rays(p.orc, oracle.opts(256, 0.0, True), o, d)
+    err = np.abs(to_np(rgb).astype(np.float64) - orgb).max(axis=1)
+    print("bf16 hash: p99.5 %.2e max %.2e" % (np.quantile(err, 0.995), err.max()))
+    assert np.quantile(err, 0.995) <= 2e-5 and err.max() <= 2e-3
+
+
+def test_hash_backward_rejected():
+    import paper_2404_11852_amd as cic
+    p = HashPair(res=32, occupancy=False)
+    o, d = synth.random_rays(16, seed=1)
+    with pytest.raises(cic.CicError):
+        cic.render_backward(p.gpu, cic.make_opts(32), torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(),
+                            torch.zeros(16, 3, device="cuda"))
