@@ -58,6 +58,26 @@ def camera(W, H, pose):
     return cic.make_camera(W, H, f, cx, cy, synth.as_f32(pose))
 
 
+# HBM bytes of one launch of the headline MLP kernel (ray order, 800x800 frame):
+# calibrated FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 from the rocprofv3 counter
+# passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
+# sources they were taken on (sha256 prefix of mlp.hip + common.h + kernels.h).
+MLP_TRAFFIC_BYTES = 4.284e9 + 0.705e9
+MLP_TRAFFIC_SRC = "ea2896db1bc6d179"
+
+
+def mlp_traffic():
+    """The counted traffic per launch, or None once the kernel sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_11852_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("mlp.hip", "common.h", "kernels.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return MLP_TRAFFIC_BYTES if h.hexdigest()[:16] == MLP_TRAFFIC_SRC else None
+
+
 def timed_frames(model, opts, cam, steps, warmup):
     """Warm up, then time exactly `steps` render_frame calls."""
     import torch
@@ -417,8 +437,9 @@ def cpu_baseline(scene, target_s=12.0):
 def profile_run():
     """Short fixed workload for hardware-counter passes: a 1 GiB device copy
     (calibrates FETCH_SIZE / WRITE_SIZE against known bytes), then two 800x800
-    frames in ray order, two in voxel order, one 8-view BF16 launch and one
-    training step."""
+    frames in ray order, two in voxel order, one frame of the multi-level
+    encoding model in each order, one 8-view BF16 launch and one training
+    step."""
     import torch
     import synth
     import paper_2404_11852_amd as cic
@@ -434,6 +455,12 @@ def profile_run():
         for _ in range(2):
             cic.render_frame(model, opts, cam)
     torch.cuda.synchronize()
+    dens, _, mlp = scene
+    hmodel = cic.Model(dens, None, mlp, density_shift=synth.DENSITY_SHIFT, hash_enc=synth.make_hash_tables(30))
+    hmodel.build_occupancy(synth.OCC_SIGMA)
+    for order in (cic.CIC_ORDER_RAY, cic.CIC_ORDER_VOXEL):
+        cic.render_frame(hmodel, cic.make_opts(256, 1e-4, True, order=order), cam)
+    torch.cuda.synchronize()
     precision_bench(scene, model.occupancy, 1)
     fwd_bwd_bench(1)
     torch.cuda.synchronize()
@@ -447,6 +474,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--order", choices=["ray", "voxel"], default="ray")
     ap.add_argument("--skip-sparw", action="store_true")
+    ap.add_argument("--skip-hash", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--skip-fwd-bwd", action="store_true")
@@ -513,12 +541,13 @@ def main():
         "order_ab": ab,
         "roofline": {"bound": "mfma", "kernel": "k_mlp_fwd_f32 (feature gather + MLP)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": mlp_traffic(),
                      "flop_per_launch": MLP_FLOP_PER_SAMPLE * samples_per_frame,
                      "ms_per_launch": mlp_ms_per},
     }
-    log("multi-level encoding workload")
-    out["hash_encoding"] = hash_bench(W, H, max(3, args.steps // 4))
+    if not args.skip_hash:
+        log("multi-level encoding workload")
+        out["hash_encoding"] = hash_bench(W, H, max(3, args.steps // 4))
     if not args.skip_sparw:
         log("SpaRW orbit")
         out["sparw"] = sparw_sweep(model, opts, W, H)
