@@ -199,6 +199,7 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
     b.rec_w = cv.take<float>(ns);
     b.rec_c = cv.take<float>(3 * ns);
     if (!voxel) b.z0 = cv.take<float>(128 * nc);
+    b.enc = cv.take<uint32_t>(16 * nc);
     if (voxel) {
         b.rec_key = cv.take<uint32_t>(ns);
         b.brick_off = cv.take<uint32_t>(n_bricks + 1);
@@ -430,6 +431,10 @@ void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, con
     if (!voxel && mlp->compute == CIC_F32) {
         StageTimer t(CIC_STAGE_EMBED, s);
         launch_ray_embed(*mlp, b, s);
+    }
+    if (mlp->compute == CIC_BF16) {
+        StageTimer t(CIC_STAGE_EMBED, s);
+        launch_ray_encode_bf16(b, s);
     }
     {
         StageTimer t(CIC_STAGE_MLP, s);

@@ -34,6 +34,7 @@ struct RenderBufs {
     float *rec_t;          // [n*N] compacted T_k (adjoint only; nullable)
     float *stage;          // [n*N][kStageStride] per-sample MLP vectors (adjoint only; nullable)
     float *z0;             // [n][128] per-ray direction term of layer 0 (ray order)
+    uint32_t *enc;         // [n][16] per-ray view encoding in BF16: lane group q's 7 inputs in words 4q..4q+3
     // voxel order
     uint32_t *rec_key;     // [n*N] brick of each live sample
     uint32_t *brick_off;   // [n_bricks+1] counts, then cursors
@@ -79,6 +80,8 @@ void launch_build_occupancy(const GridK &g, float thr, uint8_t *occ, hipStream_t
 int mlp_lds_bytes(int compute);
 template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
+// per-ray BF16 view encoding into b.enc (BF16 compute; rays with live samples)
+void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s);
 // per-ray direction term of layer 0 into b.z0 (rays with live samples)
 void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s);
 // forward with per-sample staging of x, h1, h2 (float32 grids, ray order)

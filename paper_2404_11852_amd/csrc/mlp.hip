@@ -86,6 +86,23 @@ __device__ void stage_weights_f32(const cic_mlp &m, float *lds)
 
 __device__ __forceinline__ float pick3(int i, float a, float b, float c) { return i == 0 ? a : (i == 1 ? b : c); }
 
+// View-encoding inputs of lane group q (layer-0 chunks 3-9): direction
+// component q (q = 3 pads with 0), then sin and cos of encoding pairs
+// p = 3q..3q+2, p = 4*component + octave.
+__device__ __forceinline__ void encode_group(const float d[3], int q, float x[7])
+{
+    x[0] = q < 3 ? pick3(q, d[0], d[1], d[2]) : 0.f;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+        const int p = 3 * q + jj;
+        const float a = ldexpf(pick3(p >> 2, d[0], d[1], d[2]), p & 3);
+        float sn, cs;
+        sincosf(a, &sn, &cs);
+        x[1 + 2 * jj] = sn;
+        x[2 + 2 * jj] = cs;
+    }
+}
+
 // Layer-0 inputs of one sample for this lane's group q (PE = false: only
 // the three feature channels; the direction terms come from the per-ray
 // table).
@@ -121,16 +138,7 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
         for (int c = 3; c < 10; ++c) x[c] = 0.f;
         return;
     }
-    x[3] = q < 3 ? pick3(q, d[0], d[1], d[2]) : 0.f;
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-        const int p = 3 * q + jj;
-        const float a = ldexpf(pick3(p >> 2, d[0], d[1], d[2]), p & 3);
-        float sn, cs;
-        sincosf(a, &sn, &cs);
-        x[4 + 2 * jj] = sn;
-        x[5 + 2 * jj] = cs;
-    }
+    encode_group(d, q, x + 3);
 }
 
 // Batch range of this workgroup's XCD.  Workgroups are dispatched to the 8
@@ -190,6 +198,35 @@ __global__ __launch_bounds__(128) void k_ray_embed(cic_mlp m, RenderBufs b, floa
         for (int i = 0; i < 27; ++i) acc = fmaf(w[i], pe[r][i], acc);
         z0[ray * 128 + o] = acc;
     }
+}
+
+// BF16 compute: lane group q's seven view-encoding inputs of every ray with
+// live samples, rounded to BF16 (the rounding the MLP kernel applies to its
+// inputs) and packed as 8 BF16 (last slot 0) into words 4q..4q+3 of the ray.
+__global__ __launch_bounds__(256) void k_ray_encode_bf16(RenderBufs b)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ray = t >> 2;
+    const int q = (int)(t & 3);
+    if (ray >= b.n || b.count[ray] == 0) return;
+    float d[3], x[7];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = b.rays_d[3 * ray + a];
+    encode_group(d, q, x);
+    typedef __bf16 bf8v_t __attribute__((ext_vector_type(8)));
+    bf8v_t v;
+#pragma unroll
+    for (int e = 0; e < 7; ++e) v[e] = (__bf16)x[e];
+    v[7] = (__bf16)0.0f;
+    typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+    *(u4_t *)(b.enc + ray * 16 + 4 * q) = __builtin_bit_cast(u4_t, v);
+}
+
+void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s)
+{
+    if (b.n == 0) return;
+    const int64_t threads = 4 * b.n;
+    hipLaunchKernelGGL(k_ray_encode_bf16, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, b);
 }
 
 void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s)
@@ -395,8 +432,24 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kBfWaves = 4;
-constexpr int kBfNT = 2;
+// Launch shape (measured on the 8-view workload, MLP stage): a BF16 MFMA does
+// a 16-sample tile's layer in 1/16 of the FP32 time, so each batch carries
+// little MFMA work against its dependent gather loads and its weight reads
+// from LDS; 16 wavefronts per CU (128 VGPRs each) with two tiles per batch
+// hide the loads best and read each weight fragment for 32 samples
+// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms).
+#ifndef CIC_BF_NT
+#define CIC_BF_NT 2
+#endif
+#ifndef CIC_BF_WAVES
+#define CIC_BF_WAVES 16
+#endif
+#ifndef CIC_BF_WGS
+#define CIC_BF_WGS 1
+#endif
+constexpr int kBfWaves = CIC_BF_WAVES;   // wavefronts per workgroup
+constexpr int kBfWgs = CIC_BF_WGS;       // workgroups per CU (each holds its own 53 KB of LDS weights)
+constexpr int kBfNT = CIC_BF_NT;         // 16-sample tiles per wavefront batch
 constexpr int kBfBatch = 16 * kBfNT;
 // LDS layout in 16-byte fragments, then floats
 constexpr int kBfW0 = 0;                           // [t 8][c 2][lane 64]
@@ -467,6 +520,18 @@ __device__ __forceinline__ bf8_t pack_bf8(const f4_t a, const f4_t b)
     return v;
 }
 
+// ReLU of BF16 values as 16-bit integers: a negative BF16 (sign bit set) is
+// a negative int16, so max(bits, 0) zeroes exactly the negatives (and -0).
+// Rounding to BF16 preserves sign, so this equals rounding after the ReLU.
+typedef short s8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf8_t relu_bf8(bf8_t v)
+{
+    s8_t s = __builtin_bit_cast(s8_t, v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = s[e] > 0 ? s[e] : (short)0;
+    return __builtin_bit_cast(bf8_t, s);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
@@ -492,16 +557,22 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
             valid[nt] = s < total;
             rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             float x[10];
+            bf8_t ev;
             if (valid[nt]) {
-                sample_inputs<T>(g, b, rec[nt], q, x);
+                sample_inputs<T, false>(g, b, rec[nt], q, x);
+                typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+                ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)b.rec_ray[rec[nt]] * 16 + 4 * q));
             } else {
 #pragma unroll
                 for (int c = 0; c < 10; ++c) x[c] = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) ev[e] = (__bf16)0.0f;
             }
+            // chunk 0: features 3q..3q+2 then encoding slots 0..4; chunk 1: slots 5, 6
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                xin[nt][0][e] = (__bf16)x[e];
-                xin[nt][1][e] = (__bf16)(e < 2 ? x[8 + e] : 0.f);
+                xin[nt][0][e] = e < 3 ? (__bf16)x[e] : ev[e - 3];
+                xin[nt][1][e] = e < 2 ? ev[5 + e] : (__bf16)0.0f;
             }
 
         }
@@ -528,15 +599,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt) {
-                f4_t lo = h1[2 * c][nt], hi = h1[2 * c + 1][nt];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    lo[r] = fmaxf(lo[r], 0.f);
-                    hi[r] = fmaxf(hi[r], 0.f);
-                }
-                hb[c][nt] = pack_bf8(lo, hi);
-            }
+            for (int nt = 0; nt < kBfNT; ++nt) hb[c][nt] = relu_bf8(pack_bf8(h1[2 * c][nt], h1[2 * c + 1][nt]));
         // layer 1
         f4_t h2[8][kBfNT];
 #pragma unroll
@@ -564,15 +627,9 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         for (int c = 0; c < 4; ++c) {
             const bf8_t a = frag[kBfW2 + c * 64 + lane];
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt) {
-                f4_t lo = h2[2 * c][nt], hi = h2[2 * c + 1][nt];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    lo[r] = fmaxf(lo[r], 0.f);
-                    hi[r] = fmaxf(hi[r], 0.f);
-                }
-                o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, pack_bf8(lo, hi), o3[nt], 0, 0, 0);
-            }
+            for (int nt = 0; nt < kBfNT; ++nt)
+                o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, relu_bf8(pack_bf8(h2[2 * c][nt], h2[2 * c + 1][nt])),
+                                                                 o3[nt], 0, 0, 0);
         }
         // lanes of group 0 hold rows 0..3 (colour channels 0..2) of their sample
 #pragma unroll
@@ -619,7 +676,7 @@ static void launch_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, b
                                   kLdsBf16);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus(b) * 3), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
+    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus(b) * kBfWgs), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
                        voxel ? 1 : 0);
 }
 
