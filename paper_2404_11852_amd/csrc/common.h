@@ -54,6 +54,16 @@ template <typename T> __device__ __forceinline__ float ldv(const T *p, int64_t i
 template <> __device__ __forceinline__ float ldv<float>(const float *p, int64_t i) { return p[i]; }
 template <> __device__ __forceinline__ float ldv<__half>(const __half *p, int64_t i) { return __half2float(p[i]); }
 
+// max(v, 0) and the clamp to [0, 1] on the float's bit pattern: one integer
+// instruction each, where fmaxf/fminf also canonicalise NaNs first.  Equal to
+// fmaxf(v, 0) and fminf(fmaxf(v, 0), 1) for every non-NaN v (a non-negative
+// float orders like its bits) up to the sign of a zero result.
+__device__ __forceinline__ float relu_bits(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
+__device__ __forceinline__ float clamp01_bits(float v)
+{
+    return __int_as_float(min(max(__float_as_int(v), 0), 0x3f800000));
+}
+
 // --------------------------------------------------------------------------
 // float32 geometry (decides integers; written in the same expression order
 // as the reference description, no contraction)
@@ -94,7 +104,7 @@ __device__ __forceinline__ void locate(const float x[3], const GridK &g, int i0[
         i = i < 0 ? 0 : i;
         i = i > rr[k] - 2 ? rr[k] - 2 : i;
         float f = u - (float)i;
-        fr[k] = fminf(fmaxf(f, 0.0f), 1.0f);
+        fr[k] = clamp01_bits(f);
         i0[k] = i;
     }
 }
@@ -178,7 +188,7 @@ __device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x
         i = i < 0 ? 0 : i;
         i = i > N - 1 ? N - 1 : i;
         const float f = u - (float)i;
-        fr[a] = fminf(fmaxf(f, 0.0f), 1.0f);
+        fr[a] = clamp01_bits(f);
         i0[a] = i;
     }
     const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;

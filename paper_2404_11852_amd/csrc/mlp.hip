@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h1[t][nt][r] = fmaxf(h1[t][nt][r], 0.f);
+                for (int r = 0; r < 4; ++r) h1[t][nt][r] = relu_bits(h1[t][nt][r]);
         if (STAGE) {
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
                     for (int t = 0; t < 8; ++t) {
                         f4_t v = h2[t][nt];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+                        for (int r = 0; r < 4; ++r) v[r] = relu_bits(v[r]);
                         *(f4_t *)(b.stage + rec[nt] * kStageStride + kStH2 + 16 * t + 4 * q) = v;
                     }
         }
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
                 const f4_t wc = w2l[(q * 3 + 2) * 8 + t];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float hv = fmaxf(h2[t][nt][r], 0.f);
+                    const float hv = relu_bits(h2[t][nt][r]);
                     p0 = fmaf(wa[r], hv, p0);
                     p1 = fmaf(wb[r], hv, p1);
                     p2 = fmaf(wc[r], hv, p2);
