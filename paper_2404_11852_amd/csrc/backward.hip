@@ -135,7 +135,8 @@ constexpr int kBOffW0T = kBOffW1T + 8 * 8 * 64 * 4;
 constexpr int kBOffW2 = kBOffW0T + 8 * 64 * 4;
 constexpr int kBLds = kBOffW2 + 384;
 
-__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
+__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb,
+                                                               int voxel)
 {
     extern __shared__ float lds[];
     const int nthr = blockDim.x;
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
     const f4_t *w2l = (const f4_t *)(lds + kBOffW2);
     float *dfeat_grad = bb.d_features;
 
-    for (int64_t bt = (int64_t)blockIdx.x * kBwdWaves + wave; bt < nbatch; bt += (int64_t)gridDim.x * kBwdWaves) {
+    const BatchRange br = xcd_batches(nbatch, kBwdWaves, wave);
+    for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
         int64_t rec[kBNT];
         bool valid[kBNT];
         f4_t dp1[8][kBNT];
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
         for (int nt = 0; nt < kBNT; ++nt) {
             const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
             valid[nt] = s < total;
-            rec[nt] = valid[nt] ? s : 0;
+            rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             const float *row = b.stage + rec[nt] * kStageStride;
             float dl[3] = {0.f, 0.f, 0.f};
             if (valid[nt]) {
@@ -251,6 +253,16 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
                 for (int nt = 0; nt < kBNT; ++nt)
                     df[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp0[c4][nt][rr], df[nt], 0, 0, 0);
         }
+        if (bb.df_sorted) {
+            // brick-tile mode: keep the 12 feature gradients of the sample at its
+            // position in brick order; k_fgrad_brick accumulates them
+#pragma unroll
+            for (int nt = 0; nt < kBNT; ++nt) {
+                const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
+                if (valid[nt] && q < 3) *(f4_t *)(bb.df_sorted + s * 12 + 4 * q) = df[nt];
+            }
+            continue;
+        }
 #pragma unroll
         for (int nt = 0; nt < kBNT; ++nt) {
             if (!valid[nt] || q >= 3) continue;
@@ -279,7 +291,71 @@ static int num_cus_b()
     return n > 0 ? n : 256;
 }
 
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb,
+// Feature gradients, one workgroup per brick of 8^3 voxels: the brick's
+// samples (contiguous in brick order) add their trilinear shares into a
+// 9x9x9-vertex tile of 12 channels in LDS, then the tile is added to the
+// gradient grid with one global atomic per nonzero entry, consecutive
+// entries on consecutive addresses (vertices on a brick face are shared with
+// the neighbour brick, hence atomics).
+constexpr int kTileV = kBrick + 1;
+constexpr int kTileFloats = kTileV * kTileV * kTileV * 12;
+
+__global__ __launch_bounds__(256) void k_fgrad_brick(GridK g, RenderBufs b, BackwardBufs bb)
+{
+    __shared__ float tile[kTileFloats];
+    const int64_t brick = blockIdx.x;
+    const uint32_t start = brick == 0 ? 0u : b.brick_off[brick - 1];
+    const uint32_t end = b.brick_off[brick];
+    if (start >= end) return;
+    for (int e = threadIdx.x; e < kTileFloats; e += blockDim.x) tile[e] = 0.f;
+    __syncthreads();
+    const int bz = (int)(brick % g.nb2), by = (int)((brick / g.nb2) % g.nb1), bx = (int)(brick / ((int64_t)g.nb2 * g.nb1));
+    const int base[3] = {kBrick * bx, kBrick * by, kBrick * bz};
+    for (uint32_t s = start + threadIdx.x; s < end; s += blockDim.x) {
+        const uint32_t rec = b.perm[s];
+        const uint32_t ray = b.rec_ray[rec];
+        const RayInfo inf = b.info[ray];
+        float o[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = b.rays_o[3 * (int64_t)ray + a];
+            d[a] = b.rays_d[3 * (int64_t)ray + a];
+        }
+        int i0[3];
+        float fr[3], tk;
+        sample_voxel(o, d, inf.tn, inf.delta, b.rec_k[rec], g, i0, fr, tk);
+        const float wx[2] = {1.f - fr[0], fr[0]}, wy[2] = {1.f - fr[1], fr[1]}, wz[2] = {1.f - fr[2], fr[2]};
+        const int lx = i0[0] - base[0], ly = i0[1] - base[1], lz = i0[2] - base[2];
+        const float *df = bb.df_sorted + (int64_t)s * 12;
+        float v[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) v[f] = df[f];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+            const float w = wx[dx] * wy[dy] * wz[dz];
+            float *t = tile + (((lx + dx) * kTileV + (ly + dy)) * kTileV + (lz + dz)) * 12;
+#pragma unroll
+            for (int f = 0; f < 12; ++f) atomicAdd(t + f, w * v[f]);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTileFloats; e += blockDim.x) {
+        const float val = tile[e];
+        if (val == 0.f) continue;
+        const int f = e % 12, vtx = e / 12;
+        const int vz = base[2] + vtx % kTileV, vy = base[1] + (vtx / kTileV) % kTileV, vx = base[0] + vtx / (kTileV * kTileV);
+        if (vx < g.r0 && vy < g.r1 && vz < g.r2) atomicAdd(bb.d_features + vertex_index(g, vx, vy, vz) * 12 + f, val);
+    }
+}
+
+void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
+{
+    if (b.n_bricks == 0) return;
+    hipLaunchKernelGGL(k_fgrad_brick, dim3((unsigned)b.n_bricks), dim3(256), 0, s, g, b, bb);
+}
+
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
                          hipStream_t s)
 {
     const int lds = kBLds * (int)sizeof(float);
@@ -288,7 +364,7 @@ void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, 
         (void)hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb);
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb, voxel ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -245,4 +245,22 @@ __device__ __forceinline__ float wave_sum(float v)
 
 __device__ __forceinline__ uint64_t lanes_below_mask() { return (1ull << lane_id()) - 1ull; }
 
+// Batch range of this workgroup's XCD.  Workgroups are dispatched to the 8
+// XCDs round-robin, so blocks x, x+8, x+16, ... share one L2; giving each
+// XCD one contiguous eighth of the (ray-ordered) samples keeps the grid
+// region those rays touch in that XCD's L2.  (Only performance depends on
+// the dispatch order.)
+constexpr int kXcds = 8;
+struct BatchRange {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ BatchRange xcd_batches(int64_t nbatch, int waves, int wave)
+{
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
+    const int64_t per = (nbatch + kXcds - 1) / kXcds;
+    const int64_t lo = xcd * per, hi = lo + per < nbatch ? lo + per : nbatch;
+    return {lo + (int64_t)slot * waves + wave, hi, (int64_t)nslots * waves};
+}
+
+
 }  // namespace cic

@@ -85,7 +85,7 @@ void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s);
 // per-ray direction term of layer 0 into b.z0 (rays with live samples)
 void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s);
 // forward with per-sample staging of x, h1, h2 (float32 grids, ray order)
-void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s);
+void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
 
 // warp.hip
 void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], float cmin, const float *ref_rgb,
@@ -100,6 +100,7 @@ struct BackwardBufs {
     float *d_w0, *d_b0, *d_w1, *d_b1, *d_w2, *d_b2;
     float *rec_dc;         // [n*N*3] dL/dc per live sample
     float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
+    float *df_sorted;      // [n*N][12] feature gradient per sample in brick order (brick-tile mode), else null
 };
 constexpr int kWgBlocks = 1024;
 // per-block partial products: dp0^T[x|1] (128x48), dp1^T h1 (128x128),
@@ -107,8 +108,10 @@ constexpr int kWgBlocks = 1024;
 constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 * 16;
 void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
                                hipStream_t s);
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb,
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
                          hipStream_t s);
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
+// brick-tile accumulation of the feature gradients written by the MLP backward
+void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
 
 }  // namespace cic

@@ -164,23 +164,6 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
     sample_inputs_from<T, PE>(g, r, q, x);
 }
 
-// Batch range of this workgroup's XCD.  Workgroups are dispatched to the 8
-// XCDs round-robin, so blocks x, x+8, x+16, ... share one L2; giving each
-// XCD one contiguous eighth of the (ray-ordered) samples keeps the grid
-// region those rays touch in that XCD's L2.  (Only performance depends on
-// the dispatch order.)
-constexpr int kXcds = 8;
-struct BatchRange {
-    int64_t first, end, stride;
-};
-__device__ __forceinline__ BatchRange xcd_batches(int64_t nbatch, int waves, int wave)
-{
-    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
-    const int64_t per = (nbatch + kXcds - 1) / kXcds;
-    const int64_t lo = xcd * per, hi = lo + per < nbatch ? lo + per : nbatch;
-    return {lo + (int64_t)slot * waves + wave, hi, (int64_t)nslots * waves};
-}
-
 // Per-ray direction term of layer 0: z0[ray][o] = b0[o] + sum_i W0[o][12+i] pe_i
 // over the 27 direction inputs (d, sin, cos), once per ray with live samples
 // (float32; used by the FP32 MLP in ray order).
@@ -736,9 +719,9 @@ void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, b
     else launch_fwd<T, false, true>(g, m, b, false, s);
 }
 
-void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, hipStream_t s)
+void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
-    launch_fwd<float, true, false>(g, m, b, false, s);
+    launch_fwd<float, true, false>(g, m, b, voxel, s);
 }
 
 template void launch_mlp_forward<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
