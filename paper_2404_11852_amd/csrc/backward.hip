@@ -106,7 +106,8 @@ __global__ __launch_bounds__(256) void k_bwd_composite(GridK g, OptsK op, Render
             ds *= inf.delta;
             const float raw = trilerp1(dens, g, i0, fr, 1, 0);
             const float draw = ds * sigmoidf(raw + g.shift);
-            scatter_trilinear(bb.d_density, g, i0, fr, 1, 0, draw);
+            if (bb.rec_draw) bb.rec_draw[r] = draw;   // added per brick with the feature gradients
+            else scatter_trilinear(bb.d_density, g, i0, fr, 1, 0, draw);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) bb.rec_dc[3 * r + ch] = w * gr[ch];
         }
@@ -291,14 +292,15 @@ static int num_cus_b()
     return n > 0 ? n : 256;
 }
 
-// Feature gradients, one workgroup per brick of 8^3 voxels: the brick's
-// samples (contiguous in brick order) add their trilinear shares into a
-// 9x9x9-vertex tile of 12 channels in LDS, then the tile is added to the
-// gradient grid with one global atomic per nonzero entry, consecutive
-// entries on consecutive addresses (vertices on a brick face are shared with
-// the neighbour brick, hence atomics).
+// Feature and density gradients, one workgroup per brick of 8^3 voxels: the
+// brick's samples (contiguous in brick order) add their trilinear shares
+// into a 9x9x9-vertex tile of 13 channels (12 features, raw density) in LDS,
+// then the tile is added to the gradient grids with one global atomic per
+// nonzero entry, consecutive entries on consecutive addresses (vertices on a
+// brick face are shared with the neighbour brick, hence atomics).
 constexpr int kTileV = kBrick + 1;
-constexpr int kTileFloats = kTileV * kTileV * kTileV * 12;
+constexpr int kTileCh = 13;
+constexpr int kTileFloats = kTileV * kTileV * kTileV * kTileCh;
 
 __global__ __launch_bounds__(256) void k_fgrad_brick(GridK g, RenderBufs b, BackwardBufs bb)
 {
@@ -327,25 +329,30 @@ __global__ __launch_bounds__(256) void k_fgrad_brick(GridK g, RenderBufs b, Back
         const float wx[2] = {1.f - fr[0], fr[0]}, wy[2] = {1.f - fr[1], fr[1]}, wz[2] = {1.f - fr[2], fr[2]};
         const int lx = i0[0] - base[0], ly = i0[1] - base[1], lz = i0[2] - base[2];
         const float *df = bb.df_sorted + (int64_t)s * 12;
-        float v[12];
+        float v[kTileCh];
 #pragma unroll
         for (int f = 0; f < 12; ++f) v[f] = df[f];
+        v[12] = bb.rec_draw[rec];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
             const float w = wx[dx] * wy[dy] * wz[dz];
-            float *t = tile + (((lx + dx) * kTileV + (ly + dy)) * kTileV + (lz + dz)) * 12;
+            float *t = tile + (((lx + dx) * kTileV + (ly + dy)) * kTileV + (lz + dz)) * kTileCh;
 #pragma unroll
-            for (int f = 0; f < 12; ++f) atomicAdd(t + f, w * v[f]);
+            for (int f = 0; f < kTileCh; ++f) atomicAdd(t + f, w * v[f]);
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kTileFloats; e += blockDim.x) {
         const float val = tile[e];
         if (val == 0.f) continue;
-        const int f = e % 12, vtx = e / 12;
+        const int f = e % kTileCh, vtx = e / kTileCh;
         const int vz = base[2] + vtx % kTileV, vy = base[1] + (vtx / kTileV) % kTileV, vx = base[0] + vtx / (kTileV * kTileV);
-        if (vx < g.r0 && vy < g.r1 && vz < g.r2) atomicAdd(bb.d_features + vertex_index(g, vx, vy, vz) * 12 + f, val);
+        if (vx < g.r0 && vy < g.r1 && vz < g.r2) {
+            const int64_t vi = vertex_index(g, vx, vy, vz);
+            if (f < 12) atomicAdd(bb.d_features + vi * 12 + f, val);
+            else atomicAdd(bb.d_density + vi, val);
+        }
     }
 }
 

@@ -101,6 +101,7 @@ struct BackwardBufs {
     float *rec_dc;         // [n*N*3] dL/dc per live sample
     float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
     float *df_sorted;      // [n*N][12] feature gradient per sample in brick order (brick-tile mode), else null
+    float *rec_draw;       // [n*N] raw-density gradient per live sample (brick-tile mode), else null
 };
 constexpr int kWgBlocks = 1024;
 // per-block partial products: dp0^T[x|1] (128x48), dp1^T h1 (128x128),
