@@ -62,8 +62,8 @@ def camera(W, H, pose):
 # calibrated FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 from the rocprofv3 counter
 # passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
 # sources they were taken on (sha256 prefix of mlp.hip + common.h + kernels.h).
-MLP_TRAFFIC_BYTES = 4.284e9 + 0.705e9
-MLP_TRAFFIC_SRC = "ea2896db1bc6d179"
+MLP_TRAFFIC_BYTES = 3.197e9 + 0.715e9
+MLP_TRAFFIC_SRC = "79dd15536d7ab12a"
 
 
 def mlp_traffic():
