@@ -3,10 +3,13 @@
 // finds the disoccluded pixels for step 4.
 //
 // Z-buffer: one 64-bit key per target pixel, (float bits of depth << 32) |
-// reference pixel index, combined with a 64-bit atomic min.  For positive
+// reference pixel index, combined with 64-bit atomic min (in LDS per block of
+// reference pixels, then once per touched target pixel in global memory).  For positive
 // floats the bit pattern orders like the value, so the minimum key is the
 // nearest splat and, among equal depths, the smallest reference index: the
 // result is independent of execution order and needs no locks.
+#include <climits>
+
 #include "kernels.h"
 
 namespace cic {
@@ -52,23 +55,83 @@ __device__ __forceinline__ bool angle_ok(float Xt, float Yt, float Zt, const War
     return dot / (n1 * n2) > cmin;
 }
 
+// Splat: one workgroup per 16x16 block of reference pixels.  With small
+// camera motion a block's splats land in a small target window, so the
+// workgroup first combines them in an LDS tile (64-bit LDS atomic min, the
+// same packed key) and then issues one global atomic min per touched target
+// pixel; when the window exceeds the tile it falls back to one global atomic
+// per splat.  The minimum does not depend on the order, so both give the same
+// z-buffer.
+constexpr int kSplatBlock = 16;
+constexpr int kSplatTile = 4096;   // target pixels in the LDS window (32 KB of keys)
+
 __global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera tgt, WarpT T, const float *ref_depth,
                                                     unsigned long long *zbuf)
 {
-    const int64_t src = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = (int64_t)ref.width * ref.height;
-    if (src >= n) return;
-    const float D = ref_depth[src];
-    if (D != D) return;
-    float Xt, Yt, Zt, kz;
-    warp_point(ref, T, (int)(src % ref.width), (int)(src / ref.width), D, Xt, Yt, Zt, kz);
-    if (!(Zt > 0.0f)) return;
-    const float u = tgt.f * (Xt / Zt) + tgt.cx;
-    const float v = tgt.f * (Yt / Zt) + tgt.cy;
-    if (!(u >= 0.0f && u < (float)tgt.width && v >= 0.0f && v < (float)tgt.height)) return;
-    const int64_t p = (int64_t)floorf(v) * tgt.width + (int64_t)floorf(u);
-    const unsigned long long key = ((unsigned long long)f32_bits(kz) << 32) | (unsigned long long)(uint32_t)src;
-    atomicMin(&zbuf[p], key);
+    __shared__ unsigned long long tile[kSplatTile];
+    __shared__ int box[4];   // min x, min y, max x, max y of this block's target pixels
+    const int i = blockIdx.x * kSplatBlock + (int)(threadIdx.x % kSplatBlock);
+    const int j = blockIdx.y * kSplatBlock + (int)(threadIdx.x / kSplatBlock);
+    if (threadIdx.x == 0) {
+        box[0] = INT_MAX;
+        box[1] = INT_MAX;
+        box[2] = INT_MIN;
+        box[3] = INT_MIN;
+    }
+    __syncthreads();
+    bool hit = false;
+    int px = 0, py = 0;
+    unsigned long long key = ~0ull;
+    if (i < ref.width && j < ref.height) {
+        const int64_t src = (int64_t)j * ref.width + i;
+        const float D = ref_depth[src];
+        if (D == D) {
+            float Xt, Yt, Zt, kz;
+            warp_point(ref, T, i, j, D, Xt, Yt, Zt, kz);
+            if (Zt > 0.0f) {
+                const float u = tgt.f * (Xt / Zt) + tgt.cx;
+                const float v = tgt.f * (Yt / Zt) + tgt.cy;
+                if (u >= 0.0f && u < (float)tgt.width && v >= 0.0f && v < (float)tgt.height) {
+                    hit = true;
+                    px = (int)floorf(u);
+                    py = (int)floorf(v);
+                    key = ((unsigned long long)f32_bits(kz) << 32) | (unsigned long long)(uint32_t)src;
+                }
+            }
+        }
+    }
+    // bounding box: wavefront reductions, then one LDS atomic per wavefront
+    int bx0 = hit ? px : INT_MAX, by0 = hit ? py : INT_MAX, bx1 = hit ? px : INT_MIN, by1 = hit ? py : INT_MIN;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        bx0 = min(bx0, __shfl_xor(bx0, off, kWave));
+        by0 = min(by0, __shfl_xor(by0, off, kWave));
+        bx1 = max(bx1, __shfl_xor(bx1, off, kWave));
+        by1 = max(by1, __shfl_xor(by1, off, kWave));
+    }
+    if (lane_id() == 0 && bx0 != INT_MAX) {
+        atomicMin(&box[0], bx0);
+        atomicMin(&box[1], by0);
+        atomicMax(&box[2], bx1);
+        atomicMax(&box[3], by1);
+    }
+    __syncthreads();
+    const int x0 = box[0], y0 = box[1];
+    if (x0 == INT_MAX) return;   // nothing landed (uniform: every thread reads the same box)
+    const int tw = box[2] - x0 + 1, th = box[3] - y0 + 1;
+    if ((int64_t)tw * th > kSplatTile) {
+        if (hit) atomicMin(&zbuf[(int64_t)py * tgt.width + px], key);
+        return;
+    }
+    const int n = tw * th;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = ~0ull;
+    __syncthreads();
+    if (hit) atomicMin(&tile[(py - y0) * tw + (px - x0)], key);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const unsigned long long k = tile[e];
+        if (k != ~0ull) atomicMin(&zbuf[(int64_t)(y0 + e / tw) * tgt.width + (x0 + e % tw)], k);
+    }
 }
 
 // Resolve: the z-buffer winner is the visible reference point.  With the
@@ -131,7 +194,10 @@ void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12]
     for (int k = 0; k < 12; ++k) wt.m[k] = T[k];
     launch_fill_u64(zbuf, ~0ull, nt, s);
     if (n_holes) launch_fill_u32(n_holes, 0u, 1, s);
-    hipLaunchKernelGGL(k_warp_splat, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, ref, tgt, wt, ref_depth,
+    (void)nr;
+    const dim3 grid((unsigned)((ref.width + kSplatBlock - 1) / kSplatBlock),
+                    (unsigned)((ref.height + kSplatBlock - 1) / kSplatBlock));
+    hipLaunchKernelGGL(k_warp_splat, grid, dim3(kSplatBlock * kSplatBlock), 0, s, ref, tgt, wt, ref_depth,
                        (unsigned long long *)zbuf);
     hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, nt,
                        (const unsigned long long *)zbuf, ref, wt, cmin, ref_depth, ref_rgb, tgt_rgb, tgt_depth, mask,
