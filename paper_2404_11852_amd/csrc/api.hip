@@ -205,6 +205,8 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
         b.brick_off = cv.take<uint32_t>(n_bricks + 1);
         b.brick_tmp = cv.take<uint32_t>((int64_t)scan_tmp_elems(n_bricks));
         b.perm = cv.take<uint32_t>(ns);
+        b.work_ctr = cv.take<uint32_t>(kXcds);
+        b.seg_off = cv.take<uint32_t>(n_bricks + 1);
     }
     b.n_bricks = n_bricks;
     return b;

@@ -41,6 +41,8 @@ struct RenderBufs {
     uint32_t *brick_tmp;   // block sums for the brick scan
     uint32_t *perm;        // [n*N] sample order for the MLP stage
     int64_t n_bricks;
+    uint32_t *work_ctr;    // voxel order: per-XCD segment counters of the LDS-tile MLP kernels (kXcds words)
+    uint32_t *seg_off;     // voxel order: [n_bricks+1] exclusive scan of segments per brick
     int grid_cus;          // CUs the launch stream may use, a multiple of 8 (0 = the whole device): sizes the
                            // persistent kernels' grids
 };
@@ -64,6 +66,10 @@ void launch_brick_scatter(const RenderBufs &b, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+
+// segments of at most kTileSeg samples per brick for the LDS-tile MLP kernels
+constexpr int kTileSeg = 2048;
+void launch_brick_segments(const RenderBufs &b, hipStream_t s);
 
 // upsample.hip
 void launch_upsample_bilinear(const float *lo, int w, int h, float *out, int W, int H, int s, hipStream_t st);

@@ -164,6 +164,140 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
     sample_inputs_from<T, PE>(g, r, q, x);
 }
 
+// ---------------------------------------------------------------------------
+// Voxel order with LDS-staged bricks (the memory-centric rendering of Sec.
+// IV-A): workgroups claim bricks of 8^3 voxels from a device counter, stage
+// the brick's 9^3 vertices x 12 feature channels in LDS (35 KB as float32),
+// and gather every sample of the brick from LDS.  Each feature vertex is then
+// read from the grid once per brick instead of by every sample near it.
+// ---------------------------------------------------------------------------
+constexpr int kFTileV = kBrick + 1;
+#ifndef CIC_TILE_SOA
+#define CIC_TILE_SOA 1
+#endif
+// Channel-major tile: channel ch of vertex v at ch * kFTileS + v.  The
+// channel stride is padded so that the four 16-lane groups of a wavefront
+// (channels 3q + c) start 16 banks apart.
+constexpr int kFTileS = 752;
+constexpr int kFTileFloats = CIC_TILE_SOA ? 12 * kFTileS : kFTileV * kFTileV * kFTileV * 12;
+
+// origin vertex of a brick (kept in registers by the callers)
+struct BrickBase {
+    int x, y, z;
+};
+__device__ __forceinline__ BrickBase brick_base(const GridK &g, int64_t brick)
+{
+    const int bz = (int)(brick % g.nb2), by = (int)((brick / g.nb2) % g.nb1);
+    const int bx = (int)(brick / ((int64_t)g.nb2 * g.nb1));
+    return BrickBase{kBrick * bx, kBrick * by, kBrick * bz};
+}
+
+template <typename T>
+__device__ void load_feature_tile(const GridK &g, const BrickBase base, float *tile)
+{
+    const T *feat = (const T *)g.features;
+    for (int e = threadIdx.x; e < kFTileV * kFTileV * kFTileV * 3; e += blockDim.x) {
+        const int vtx = e / 3, part = e - 3 * vtx;
+        const int lz = vtx % kFTileV, ly = (vtx / kFTileV) % kFTileV, lx = vtx / (kFTileV * kFTileV);
+        const int vx = base.x + lx, vy = base.y + ly, vz = base.z + lz;
+        f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+        if (vx < g.r0 && vy < g.r1 && vz < g.r2) {
+            const int64_t off = vertex_index(g, vx, vy, vz) * 12 + 4 * part;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = ldv(feat, off + c);
+        }
+        if (CIC_TILE_SOA) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tile[(4 * part + c) * kFTileS + vtx] = v[c];
+        } else {
+            *(f4_t *)(tile + vtx * 12 + 4 * part) = v;
+        }
+    }
+}
+
+// Features 3q..3q+2 of a sample in cell i0 of the staged brick (same
+// interpolation order as the gather from the grid).
+__device__ __forceinline__ void tile_gather3(const float *tile, const BrickBase base, const int i0[3], const float fr[3],
+                                             int q, float x[3])
+{
+    const int lx = i0[0] - base.x, ly = i0[1] - base.y, lz = i0[2] - base.z;
+    const int vtx = (lx * kFTileV + ly) * kFTileV + lz;
+    const int vs = CIC_TILE_SOA ? 1 : 12, cs = CIC_TILE_SOA ? kFTileS : 1;
+    const int sx = kFTileV * kFTileV * vs, sy = kFTileV * vs, sz = vs;
+    const float *t = tile + vtx * vs + 3 * q * cs;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float *u = t + c * cs;
+        const float v000 = u[0], v001 = u[sz], v010 = u[sy], v011 = u[sy + sz];
+        const float v100 = u[sx], v101 = u[sx + sz], v110 = u[sx + sy], v111 = u[sx + sy + sz];
+        const float c00 = lerpf(v000, v001, fr[2]), c01 = lerpf(v010, v011, fr[2]);
+        const float c10 = lerpf(v100, v101, fr[2]), c11 = lerpf(v110, v111, fr[2]);
+        const float c0 = lerpf(c00, c01, fr[1]), c1 = lerpf(c10, c11, fr[1]);
+        x[c] = lerpf(c0, c1, fr[0]);
+    }
+}
+
+// Inputs of one sample from the staged brick: features from LDS, and (PE)
+// the view encoding.
+template <bool PE>
+__device__ __forceinline__ void sample_inputs_tile(const GridK &g, const RenderBufs &b, int64_t rec, int q,
+                                                   const float *tile, const BrickBase base, float x[10], uint32_t &ray)
+{
+    SampleRay r;
+    ray = b.rec_ray[rec];
+    load_sample_ray(b, ray, b.rec_k[rec], r);
+    int i0[3];
+    float fr[3], tk;
+    sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
+    tile_gather3(tile, base, i0, fr, q, x);
+    if (!PE) {
+#pragma unroll
+        for (int c = 3; c < 10; ++c) x[c] = 0.f;
+        return;
+    }
+    encode_group(r.d, q, x + 3);
+}
+
+// Claim the next segment (up to kTileSeg samples of one brick) for this
+// workgroup.  The segment list is split into kXcds contiguous ranges, one
+// per XCD, each drained through its own counter: the workgroups sharing an
+// L2 then work through neighbouring bricks (and the rays crossing them)
+// instead of the whole chip's in-flight window.  Thread 0 claims and
+// locates the segment and publishes it in LDS; returns false once this
+// XCD's range is exhausted (every workgroup of the XCD then ends).  Large
+// bricks are shared by several workgroups, each staging the brick's tile.
+struct TileWork {
+    int64_t brick;
+    uint32_t start, end;
+};
+__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w)
+{
+    __syncthreads();   // every wave is done with the previous segment and tile
+    if (threadIdx.x == 0) {
+        const int xcd = blockIdx.x % kXcds;
+        const uint64_t nseg = b.seg_off[b.n_bricks];
+        const uint64_t k = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, 1u);
+        TileWork t{-1, 0u, 0u};
+        if (k < nseg * (xcd + 1) / kXcds) {
+            // brick: the last index with seg_off[brick] <= k
+            int64_t lo = 0, hi = b.n_bricks;   // invariant: seg_off[lo] <= k < seg_off[hi]
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (b.seg_off[mid] <= k) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t bstart = lo == 0 ? 0u : b.brick_off[lo - 1], bend = b.brick_off[lo];
+            t.brick = lo;
+            t.start = bstart + ((uint32_t)k - b.seg_off[lo]) * (uint32_t)kTileSeg;
+            t.end = min(bend, t.start + (uint32_t)kTileSeg);
+        }
+        *slot = t;
+    }
+    __syncthreads();
+    w = *slot;
+    return w.brick >= 0;
+}
+
 // Per-ray direction term of layer 0: z0[ray][o] = b0[o] + sum_i W0[o][12+i] pe_i
 // over the 27 direction inputs (d, sin, cos), once per ray with live samples
 // (float32; used by the FP32 MLP in ray order).
@@ -556,36 +690,45 @@ __device__ __forceinline__ bf8_t relu_bf8(bf8_t v)
     return __builtin_bit_cast(bf8_t, s);
 }
 
-template <typename T>
+// TILE: voxel order with the brick's features staged in LDS (dense grids).
+template <typename T, bool TILE>
 __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
     extern __shared__ float lds_raw[];
     bf8_t *frag = (bf8_t *)lds_raw;
     float *fl = lds_raw + kBfFrags * 4;
+    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;   // TILE only
+    __shared__ TileWork seg_slot;
     stage_weights_bf16(m, frag, fl);
     __syncthreads();
 
     const int lane = lane_id(), q = lane >> 4, j = lane & 15;
     const int wave = threadIdx.x / 64;
     const int64_t total = (int64_t)b.offsets[b.n];
-    const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
-    const BatchRange br = xcd_batches(nbatch, kBfWaves, wave);
 
-    for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
+    // one batch of kBfNT tiles: samples s0 + nt*16 + j below send (TILE:
+    // of the brick staged with origin base)
+    auto batch = [&](int64_t s0, int64_t send, const BrickBase base) {
         bf8_t xin[kBfNT][2];
         int64_t rec[kBfNT];
         bool valid[kBfNT];
 #pragma unroll
         for (int nt = 0; nt < kBfNT; ++nt) {
-            const int64_t s = bt * kBfBatch + nt * 16 + j;
-            valid[nt] = s < total;
+            const int64_t s = s0 + nt * 16 + j;
+            valid[nt] = s < send;
             rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             float x[10];
             bf8_t ev;
             if (valid[nt]) {
-                sample_inputs<T, false>(g, b, rec[nt], q, x);
+                uint32_t ray;
+                if (TILE) {
+                    sample_inputs_tile<false>(g, b, rec[nt], q, tile, base, x, ray);
+                } else {
+                    sample_inputs<T, false>(g, b, rec[nt], q, x);
+                    ray = b.rec_ray[rec[nt]];
+                }
                 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
-                ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)b.rec_ray[rec[nt]] * 16 + 4 * q));
+                ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)ray * 16 + 4 * q));
             } else {
 #pragma unroll
                 for (int c = 0; c < 10; ++c) x[c] = 0.f;
@@ -665,6 +808,22 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
                 out[2] = sigmoidf(o3[nt][2]);
             }
         }
+    };
+
+    if (TILE) {
+        TileWork w;
+        while (claim_segment(b, &seg_slot, w)) {
+            const BrickBase base = brick_base(g, w.brick);
+            load_feature_tile<T>(g, base, tile);
+            __syncthreads();
+            const int64_t nb = ((int64_t)w.end - w.start + kBfBatch - 1) / kBfBatch;
+            for (int64_t bi = wave; bi < nb; bi += kBfWaves)
+                batch((int64_t)w.start + bi * kBfBatch, (int64_t)w.end, base);
+        }
+    } else {
+        const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
+        const BatchRange br = xcd_batches(nbatch, kBfWaves, wave);
+        for (int64_t bt = br.first; bt < br.end; bt += br.stride) batch(bt * kBfBatch, total, BrickBase{0, 0, 0});
     }
 }
 
@@ -691,17 +850,34 @@ static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bo
                        voxel ? 1 : 0);
 }
 
+#ifndef CIC_VOXEL_TILE
+#define CIC_VOXEL_TILE 1
+#endif
+template <typename T, bool TILE>
+static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+{
+    const int lds = kLdsBf16 + (TILE ? kFTileFloats * (int)sizeof(float) : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T, TILE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
+        attr_set = true;
+    }
+    if (TILE) {
+        launch_brick_segments(b, s);
+        launch_fill_u32(b.work_ctr, 0u, kXcds, s);
+    }
+    // TILE: at least one workgroup per XCD range of segments
+    const int grid = TILE ? std::max(num_cus(b) * kBfWgs, kXcds) : num_cus(b) * kBfWgs;
+    hipLaunchKernelGGL((k_mlp_fwd_bf16<T, TILE>), dim3(grid), dim3(kBfWaves * 64), lds, s, g, m, b,
+                       voxel ? 1 : 0);
+}
+
 template <typename T>
 static void launch_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kLdsBf16);
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((k_mlp_fwd_bf16<T>), dim3(num_cus(b) * kBfWgs), dim3(kBfWaves * 64), kLdsBf16, s, g, m, b,
-                       voxel ? 1 : 0);
+    if (CIC_VOXEL_TILE && voxel && g.hlevels == 0) launch_bf16_k<T, true>(g, m, b, true, s);
+    else launch_bf16_k<T, false>(g, m, b, voxel, s);
 }
 
 // FP32 in ray order uses the per-ray direction table (b.z0 must be filled

@@ -243,6 +243,23 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// Segments per brick (ceil(count / kTileSeg)) into seg_off, then their
+// exclusive scan: brick k owns segments seg_off[k] .. seg_off[k+1]-1.
+__global__ void k_brick_segments(RenderBufs b)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n_bricks) return;
+    const uint32_t start = k == 0 ? 0u : b.brick_off[k - 1], end = b.brick_off[k];
+    b.seg_off[k] = (end - start + (uint32_t)kTileSeg - 1u) / (uint32_t)kTileSeg;
+}
+
+void launch_brick_segments(const RenderBufs &b, hipStream_t s)
+{
+    if (b.n_bricks > 0)
+        hipLaunchKernelGGL(k_brick_segments, dim3((unsigned)((b.n_bricks + 255) / 256)), dim3(256), 0, s, b);
+    launch_exclusive_scan(b.seg_off, b.seg_off, b.brick_tmp, b.n_bricks, s);   // also writes the total
+}
+
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_u8, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
