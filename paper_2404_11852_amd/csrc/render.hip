@@ -129,12 +129,12 @@ __device__ __forceinline__ int run_length(uint64_t heads, int active)
 }
 
 // One wavefront per ray copies its live samples to their compacted position
-// (ray-order), and in voxel mode tags each with its brick and counts bricks.
-__global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxel)
+// (ray-order), and in voxel mode tags each with its brick and adds each run
+// of equal bricks to counts[brick] (global counters or an LDS histogram).
+__device__ __forceinline__ void compact_ray(const GridK &g, const RenderBufs &b, int64_t ray, bool voxel,
+                                            uint32_t *counts)
 {
     const int lane = lane_id();
-    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
-    if (ray >= b.n) return;
     const uint32_t cnt = b.count[ray];
     if (cnt == 0) return;
     const uint32_t off = b.offsets[ray];
@@ -170,14 +170,50 @@ __global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxe
         if (voxel) {
             const int active = (int)min(cnt - j0, (uint32_t)kWave);
             const uint64_t heads = run_heads(key, act);
-            if ((heads >> lane) & 1ull) atomicAdd(&b.brick_off[key], (uint32_t)run_length(heads, active));
+            if ((heads >> lane) & 1ull) atomicAdd(&counts[key], (uint32_t)run_length(heads, active));
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxel)
+{
+    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
+    if (ray >= b.n) return;
+    compact_ray(g, b, ray, voxel != 0, b.brick_off);
+}
+
+// Voxel mode with an LDS histogram of the bricks: a block compacts
+// kHistRays consecutive rays, counting their runs in LDS, and then adds each
+// brick it touched to the global count once.  The rays of a block cross
+// largely the same bricks, so this takes far fewer device-wide atomics than
+// one per run.
+constexpr int kHistBins = 16384;   // largest brick count of the LDS path (64 KB)
+constexpr int kHistRays = 256;     // rays per block
+
+__global__ __launch_bounds__(256) void k_compact_hist(GridK g, RenderBufs b)
+{
+    extern __shared__ uint32_t hist[];
+    for (int64_t i = threadIdx.x; i < b.n_bricks; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const int64_t ray0 = (int64_t)blockIdx.x * kHistRays;
+    const int64_t ray1 = ray0 + kHistRays < b.n ? ray0 + kHistRays : b.n;
+    for (int64_t ray = ray0 + threadIdx.x / kWave; ray < ray1; ray += blockDim.x / kWave)
+        compact_ray(g, b, ray, true, hist);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < b.n_bricks; i += blockDim.x) {
+        const uint32_t c = hist[i];
+        if (c) atomicAdd(&b.brick_off[i], c);
     }
 }
 
 void launch_compact(const GridK &g, const RenderBufs &b, bool voxel_keys, hipStream_t s)
 {
     if (b.n == 0) return;
+    if (voxel_keys && b.n_bricks <= kHistBins) {
+        const unsigned blocks = (unsigned)((b.n + kHistRays - 1) / kHistRays);
+        hipLaunchKernelGGL(k_compact_hist, dim3(blocks), dim3(256), b.n_bricks * sizeof(uint32_t), s, g, b);
+        return;
+    }
     const unsigned blocks = (unsigned)((b.n + kRayWaves - 1) / kRayWaves);
     hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, g, b, voxel_keys ? 1 : 0);
 }
@@ -208,9 +244,57 @@ __global__ __launch_bounds__(256) void k_brick_scatter(RenderBufs b)
     }
 }
 
+// LDS-histogram scatter over the same blocks of kHistRays rays, whose
+// samples are one contiguous range of records: count the block's samples
+// per brick in LDS, reserve each touched brick's share of the global cursor
+// with one atomic, then hand out positions from the LDS cursors (one LDS
+// atomic per run of equal bricks).
+__global__ __launch_bounds__(256) void k_brick_scatter_hist(RenderBufs b)
+{
+    extern __shared__ uint32_t hist[];
+    const int lane = lane_id(), wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+    for (int64_t i = threadIdx.x; i < b.n_bricks; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const int64_t ray0 = (int64_t)blockIdx.x * kHistRays;
+    const int64_t ray1 = ray0 + kHistRays < b.n ? ray0 + kHistRays : b.n;
+    const uint32_t s0 = b.offsets[ray0], s1 = b.offsets[ray1];
+    for (uint32_t w0 = s0 + (uint32_t)wave * kWave; w0 < s1; w0 += (uint32_t)nwaves * kWave) {
+        const uint32_t sidx = w0 + lane;
+        const bool act = sidx < s1;
+        const uint32_t key = act ? b.rec_key[sidx] : 0xffffffffu;
+        const int active = (int)min(s1 - w0, (uint32_t)kWave);
+        const uint64_t heads = run_heads(key, act);
+        if ((heads >> lane) & 1ull) atomicAdd(&hist[key], (uint32_t)run_length(heads, active));
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < b.n_bricks; i += blockDim.x) {
+        const uint32_t c = hist[i];
+        if (c) hist[i] = atomicAdd(&b.brick_off[i], c);
+    }
+    __syncthreads();
+    for (uint32_t w0 = s0 + (uint32_t)wave * kWave; w0 < s1; w0 += (uint32_t)nwaves * kWave) {
+        const uint32_t sidx = w0 + lane;
+        const bool act = sidx < s1;
+        const uint32_t key = act ? b.rec_key[sidx] : 0xffffffffu;
+        const int active = (int)min(s1 - w0, (uint32_t)kWave);
+        const uint64_t heads = run_heads(key, act);
+        uint32_t base = 0;
+        if ((heads >> lane) & 1ull) base = atomicAdd(&hist[key], (uint32_t)run_length(heads, active));
+        const uint64_t upto = heads & ((lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1ull));
+        const int head = upto ? (63 - __clzll((long long)upto)) : 0;
+        const uint32_t hb = __shfl(base, head, kWave);
+        if (act) b.perm[hb + (uint32_t)(lane - head)] = sidx;
+    }
+}
+
 void launch_brick_scatter(const RenderBufs &b, hipStream_t s)
 {
     if (b.n == 0) return;
+    if (b.n_bricks <= kHistBins) {
+        const unsigned blocks = (unsigned)((b.n + kHistRays - 1) / kHistRays);
+        hipLaunchKernelGGL(k_brick_scatter_hist, dim3(blocks), dim3(256), b.n_bricks * sizeof(uint32_t), s, b);
+        return;
+    }
     const unsigned blocks = (unsigned)((b.n + kRayWaves - 1) / kRayWaves);
     hipLaunchKernelGGL(k_brick_scatter, dim3(blocks), dim3(256), 0, s, b);
 }
