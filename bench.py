@@ -62,8 +62,8 @@ def camera(W, H, pose):
 # calibrated FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 from the rocprofv3 counter
 # passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
 # sources they were taken on (sha256 prefix of mlp.hip + common.h + kernels.h).
-MLP_TRAFFIC_BYTES = 3.197e9 + 0.715e9
-MLP_TRAFFIC_SRC = "79dd15536d7ab12a"
+MLP_TRAFFIC_BYTES = 3.160e9 + 0.714e9
+MLP_TRAFFIC_SRC = "d68279207071f018"
 
 
 def mlp_traffic():
@@ -315,9 +315,10 @@ def precision_bench(scene, occ, steps):
     o = torch.cat([r[0] for r in rays]).contiguous()
     d = torch.cat([r[1] for r in rays]).contiguous()
     go = cic.make_opts(256, 1e-4, True)
+    gv = cic.make_opts(256, 1e-4, True, order=cic.CIC_ORDER_VOXEL)
     out = {}
     imgs = {}
-    for name, model in (("bf16", g16), ("fp32", g32)):
+    for name, model, go in (("bf16", g16, go), ("bf16_voxel", g16, gv), ("fp32", g32, go)):
         cic.render_rays(model, go, o, d)
         n_eval = torch.zeros(1, dtype=torch.int64, device="cuda:0")
         torch.cuda.synchronize()
@@ -335,13 +336,16 @@ def precision_bench(scene, occ, steps):
                      "fps_800x800_per_view": 8 * steps / (t1 - t0), "evaluated_samples": ne,
                      "stage_ms": {k: v[0] / steps for k, v in st.items() if v[1]}}
     out["speedup_bf16_vs_fp32"] = out["bf16"]["samples_per_s"] / out["fp32"]["samples_per_s"]
+    out["speedup_bf16_voxel_vs_fp32"] = out["bf16_voxel"]["samples_per_s"] / out["fp32"]["samples_per_s"]
+    out["bf16_voxel_equals_ray_order"] = bool(torch.equal(imgs["bf16_voxel"], imgs["bf16"]))
     out["psnr_bf16_vs_fp32_gpu_db"] = psnr(imgs["bf16"], imgs["fp32"])
     out["max_abs_bf16_vs_fp32_gpu"] = float((imgs["bf16"] - imgs["fp32"]).abs().max().item())
-    mlp_ms = out["bf16"]["stage_ms"].get("mlp", 0.0)
-    if mlp_ms > 0:
-        ach = MLP_FLOP_PER_SAMPLE * out["bf16"]["evaluated_samples"] / (mlp_ms * 1e-3) / 1e12
-        out["bf16_mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
-                                    "frac": ach / 2500.0}
+    for name in ("bf16", "bf16_voxel"):
+        mlp_ms = out[name]["stage_ms"].get("mlp", 0.0)
+        if mlp_ms > 0:
+            ach = MLP_FLOP_PER_SAMPLE * out[name]["evaluated_samples"] / (mlp_ms * 1e-3) / 1e12
+            out[name + "_mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
+                                           "frac": ach / 2500.0}
     out["workload"] = "8 views x 800x800 (5.12M rays, one call), 160^3 grid, 256 samples, skip + termination"
     return out
 
@@ -438,8 +442,8 @@ def profile_run():
     """Short fixed workload for hardware-counter passes: a 1 GiB device copy
     (calibrates FETCH_SIZE / WRITE_SIZE against known bytes), then two 800x800
     frames in ray order, two in voxel order, one frame of the multi-level
-    encoding model in each order, one 8-view BF16 launch and one training
-    step."""
+    encoding model in each order, the 8-view precision-path launches (BF16 in
+    ray and in voxel order, FP32) and one training step."""
     import torch
     import synth
     import paper_2404_11852_amd as cic

@@ -189,6 +189,12 @@ __global__ __launch_bounds__(256) void k_compact(GridK g, RenderBufs b, int voxe
 // one per run.
 constexpr int kHistBins = 16384;   // largest brick count of the LDS path (64 KB)
 constexpr int kHistRays = 256;     // rays per block
+// The LDS path needs enough blocks to fill the chip (small launches, such as
+// a training step's few thousand rays, keep the per-run global atomics).
+static bool use_hist(const RenderBufs &b)
+{
+    return b.n_bricks <= kHistBins && b.n >= (int64_t)kHistRays * 512;
+}
 
 __global__ __launch_bounds__(256) void k_compact_hist(GridK g, RenderBufs b)
 {
@@ -209,7 +215,7 @@ __global__ __launch_bounds__(256) void k_compact_hist(GridK g, RenderBufs b)
 void launch_compact(const GridK &g, const RenderBufs &b, bool voxel_keys, hipStream_t s)
 {
     if (b.n == 0) return;
-    if (voxel_keys && b.n_bricks <= kHistBins) {
+    if (voxel_keys && use_hist(b)) {
         const unsigned blocks = (unsigned)((b.n + kHistRays - 1) / kHistRays);
         hipLaunchKernelGGL(k_compact_hist, dim3(blocks), dim3(256), b.n_bricks * sizeof(uint32_t), s, g, b);
         return;
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(256) void k_brick_scatter_hist(RenderBufs b)
 void launch_brick_scatter(const RenderBufs &b, hipStream_t s)
 {
     if (b.n == 0) return;
-    if (b.n_bricks <= kHistBins) {
+    if (use_hist(b)) {
         const unsigned blocks = (unsigned)((b.n + kHistRays - 1) / kHistRays);
         hipLaunchKernelGGL(k_brick_scatter_hist, dim3(blocks), dim3(256), b.n_bricks * sizeof(uint32_t), s, b);
         return;

@@ -45,10 +45,13 @@ def _assert_equal(a, b):
 
 
 @pytest.mark.parametrize("storage", [torch.float32, torch.float16])
-@pytest.mark.parametrize("n_rays", [1, 7, 1000, 4099])
+@pytest.mark.parametrize("n_rays", [1, 7, 1000, 4099, 256 * 512 + 77])
 def test_voxel_tiles_equal_ray_order_ragged(storage, n_rays):
     """Ragged ray counts through a 48^3 grid (6^3 bricks): segments of
-    several bricks, partial last segments, bricks shared by workgroups."""
+    several bricks, partial last segments, bricks shared by workgroups.  The
+    largest count takes the LDS-histogram compaction (blocks of 256 rays,
+    used from 512 blocks up) with a ragged last block; the others take the
+    per-run global counters."""
     print_case("voxel tiles vs ray order, 48^3, %d rays, %s" % (n_rays, storage))
     m = _model(48, storage)
     rng = np.random.default_rng(n_rays)
