@@ -29,6 +29,21 @@ METRIC = "ray samples/s + 800x800 FPS (full vs SpaRW); fwd+bwd samples/s; BF16 v
 MLP_FLOP_PER_SAMPLE = 2 * (12 * 128 + 128 * 128 + 128 * 3)   # 36,608 useful FLOP
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# Training step, per evaluated sample, on FP32 MFMA: the forward render (as
+# above), the adjoint's recomputed forward on the full 39-wide input, the MLP
+# backward (W1^T dp1 and the feature rows of W0^T dp0) and the weight
+# gradients (outer products of the three layers).
+STAGED_FWD_FLOP_PER_SAMPLE = 2 * (39 * 128 + 128 * 128 + 128 * 3)   # 43,520
+BWD_FLOP_PER_SAMPLE = 2 * (128 * 128 + 12 * 128)                     # 35,840
+WGRAD_FLOP_PER_SAMPLE = 2 * (128 * 39 + 128 * 128 + 3 * 128)        # 43,520
+# Compositing adjoint, algorithmic bytes per live sample: weight, colour and
+# distance in, density and colour gradients out (4 + 12 + 4 + 4 + 12 + 4).
+BWD_COMPOSITE_BYTES_PER_SAMPLE = 40
+# Warp of a W x H reference into a W x H target, algorithmic bytes per pixel:
+# reference colour + z-depth read (16), z-buffer clear (8), one 64-bit
+# atomic per splat (8), resolve: z-buffer read (8), winner colour + depth
+# read (16), colour, depth and mask written (12 + 4 + 1), hole list (~3).
+WARP_BYTES_PER_PIXEL = 76
 
 
 def log(msg):
@@ -107,6 +122,7 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0,
     import torch
     import synth
     import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
     poses = [synth.orbit_pose(k) for k in range(n_frames)]
     refs = list(range(0, n_frames, ref_every))
     cams = [camera(W, H, p) for p in poses]
@@ -145,6 +161,7 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0,
     # per-target time, references excluded
     ref_rgbd = {r: cic.render_frame(model, opts, cams[r])[:2] for r in refs}
     torch.cuda.synchronize()
+    _lib.timing_enable(True)
     tt0 = time.perf_counter()
     for k in range(n_frames):
         if k in refs:
@@ -154,6 +171,8 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0,
         cic.render_frame_sparw(model, sopts, cams[r], ref_rgbd[r][0], ref_rgbd[r][1], cams[k], torch.from_numpy(T))
     torch.cuda.synchronize()
     tt1 = time.perf_counter()
+    st = _lib.timing_read()
+    _lib.timing_enable(False)
     full_s = None
     if full is None:
         full_t0 = time.perf_counter()
@@ -170,6 +189,12 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0,
         "mask_fraction_mean": sum(fr) / len(fr), "mask_fraction_max": max(fr),
         "psnr_vs_full_mean_db": sum(ps) / len(ps), "psnr_vs_full_min_db": min(ps),
     }
+    warp_ms, warp_n = st["warp"]
+    if warp_n:
+        gbs = WARP_BYTES_PER_PIXEL * W * H / (warp_ms / warp_n * 1e-3) / 1e9
+        res["warp_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                "frac": gbs / PEAK_HBM_GBS, "ms_per_warp": warp_ms / warp_n,
+                                "bytes_per_warp": WARP_BYTES_PER_PIXEL * W * H}
     if full_s is not None:
         res["fps_full_render"] = n_frames / full_s
         res["speedup_vs_full"] = full_s / (t1 - t0)
@@ -401,10 +426,22 @@ def fwd_bwd_bench(steps):
     st = _lib.timing_read()
     _lib.timing_enable(False)
     ne = int(n_eval.item()) / steps
-    return {"samples_per_s": ne * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
-            "evaluated_samples_per_step": ne,
-            "stage_ms_per_step": {k: v[0] / steps for k, v in st.items() if v[1]},
-            "workload": "8192 rays from 8 views, 160^3 model grids N(0,0.01), 256 samples, fwd + adjoint, FP32"}
+    sm = {k: v[0] / steps for k, v in st.items() if v[1]}
+    out = {"samples_per_s": ne * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+           "evaluated_samples_per_step": ne, "stage_ms_per_step": sm,
+           "workload": "8192 rays from 8 views, 160^3 model grids N(0,0.01), 256 samples, fwd + adjoint, FP32"}
+    mfma_ms = sum(sm.get(k, 0.0) for k in ("mlp", "bwd_mlp", "bwd_wgrad"))
+    if mfma_ms > 0:
+        flop = (MLP_FLOP_PER_SAMPLE + STAGED_FWD_FLOP_PER_SAMPLE + BWD_FLOP_PER_SAMPLE + WGRAD_FLOP_PER_SAMPLE) * ne
+        ach = flop / (mfma_ms * 1e-3) / 1e12
+        out["mfma_roofline"] = {"bound": "mfma", "stages": "mlp + bwd_mlp + bwd_wgrad", "achieved": ach,
+                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                                "whole_step_frac": flop / (out["ms_per_step"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    if sm.get("bwd_composite", 0.0) > 0:
+        gbs = BWD_COMPOSITE_BYTES_PER_SAMPLE * ne / (sm["bwd_composite"] * 1e-3) / 1e9
+        out["bwd_composite_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "frac": gbs / PEAK_HBM_GBS}
+    return out
 
 
 def cpu_baseline(scene, target_s=12.0):

@@ -136,50 +136,82 @@ __global__ __launch_bounds__(256) void k_warp_splat(cic_camera ref, cic_camera t
 
 // Resolve: the z-buffer winner is the visible reference point.  With the
 // angle test on (cmin >= -1) a finite winner that fails it makes the pixel a
-// hole, as does an empty z-buffer entry.  Holes are appended to the hole list
-// with one atomic per wavefront.
+// hole, as does an empty z-buffer entry.  A block resolves kResolvePasses x
+// 256 consecutive target pixels, keeps each pass's hole flags, reserves the
+// block's share of the hole list with one atomic and writes its holes in
+// pixel order (an LDS prefix over the passes' wavefront counts), so the list
+// takes one device-wide atomic per block instead of one per wavefront.
+constexpr int kResolvePasses = 8;
+constexpr int kResolveWaves = 4;   // 256 threads
+
 __global__ __launch_bounds__(256) void k_warp_resolve(int64_t np, const unsigned long long *zbuf, cic_camera ref,
                                                       WarpT T, float cmin, const float *ref_depth,
                                                       const float *ref_rgb, float *tgt_rgb, float *tgt_depth,
                                                       uint8_t *mask, int32_t *src_index, int32_t *hole_idx,
                                                       uint32_t *n_holes)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = p < np;
-    const unsigned long long key = in ? zbuf[p] : ~0ull;
-    const uint32_t s = (uint32_t)(key & 0xffffffffull);
-    bool hole = in && key == ~0ull;
-    if (in && !hole && cmin >= -1.0f) {
-        const float D = ref_depth[s];
-        if (D != INFINITY) {
-            float Xt, Yt, Zt, kz;
-            warp_point(ref, T, (int)(s % (uint32_t)ref.width), (int)(s / (uint32_t)ref.width), D, Xt, Yt, Zt, kz);
-            hole = !angle_ok(Xt, Yt, Zt, T, cmin);
+    __shared__ uint32_t wave_cnt[kResolvePasses * kResolveWaves];
+    __shared__ uint32_t block_base;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const int64_t p0 = (int64_t)blockIdx.x * kResolvePasses * 256;
+    uint32_t holes = 0;   // bit i: the pixel of pass i is a hole
+#pragma unroll
+    for (int it = 0; it < kResolvePasses; ++it) {
+        const int64_t p = p0 + it * 256 + threadIdx.x;
+        const bool in = p < np;
+        const unsigned long long key = in ? zbuf[p] : ~0ull;
+        const uint32_t s = (uint32_t)(key & 0xffffffffull);
+        bool hole = in && key == ~0ull;
+        if (in && !hole && cmin >= -1.0f) {
+            const float D = ref_depth[s];
+            if (D != INFINITY) {
+                float Xt, Yt, Zt, kz;
+                warp_point(ref, T, (int)(s % (uint32_t)ref.width), (int)(s / (uint32_t)ref.width), D, Xt, Yt, Zt,
+                           kz);
+                hole = !angle_ok(Xt, Yt, Zt, T, cmin);
+            }
         }
-    }
-    if (in) {
-        if (hole) {
-            tgt_rgb[3 * p] = tgt_rgb[3 * p + 1] = tgt_rgb[3 * p + 2] = 0.f;
-            tgt_depth[p] = 0.f;
-            mask[p] = 1;
-            if (src_index) src_index[p] = -1;
-        } else {
-            tgt_rgb[3 * p] = ref_rgb[3 * (int64_t)s];
-            tgt_rgb[3 * p + 1] = ref_rgb[3 * (int64_t)s + 1];
-            tgt_rgb[3 * p + 2] = ref_rgb[3 * (int64_t)s + 2];
-            tgt_depth[p] = __uint_as_float((uint32_t)(key >> 32));
-            mask[p] = 0;
-            if (src_index) src_index[p] = (int32_t)s;
+        if (in) {
+            if (hole) {
+                tgt_rgb[3 * p] = tgt_rgb[3 * p + 1] = tgt_rgb[3 * p + 2] = 0.f;
+                tgt_depth[p] = 0.f;
+                mask[p] = 1;
+                if (src_index) src_index[p] = -1;
+            } else {
+                tgt_rgb[3 * p] = ref_rgb[3 * (int64_t)s];
+                tgt_rgb[3 * p + 1] = ref_rgb[3 * (int64_t)s + 1];
+                tgt_rgb[3 * p + 2] = ref_rgb[3 * (int64_t)s + 2];
+                tgt_depth[p] = __uint_as_float((uint32_t)(key >> 32));
+                mask[p] = 0;
+                if (src_index) src_index[p] = (int32_t)s;
+            }
         }
-    }
-    if (hole_idx) {
         const uint64_t hm = __ballot(hole);
-        if (hm) {
-            uint32_t base = 0;
-            const int leader = __ffsll((unsigned long long)hm) - 1;
-            if (lane_id() == leader) base = atomicAdd(n_holes, (uint32_t)__popcll(hm));
-            base = __shfl(base, leader, kWave);
-            if (hole) hole_idx[base + (uint32_t)__popcll(hm & lanes_below_mask())] = (int32_t)p;
+        if (lane == 0) wave_cnt[it * kResolveWaves + wave] = (uint32_t)__popcll(hm);
+        holes |= hole ? (1u << it) : 0u;
+    }
+    if (!hole_idx) return;   // uniform over the grid
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // exclusive prefix over (pass, wave) in pixel order, then the block's reservation
+        uint32_t run = 0;
+        for (int i = 0; i < kResolvePasses * kResolveWaves; ++i) {
+            const uint32_t c = wave_cnt[i];
+            wave_cnt[i] = run;
+            run += c;
+        }
+        block_base = run ? atomicAdd(n_holes, run) : 0u;
+    }
+    __syncthreads();
+    const uint32_t base = block_base;
+#pragma unroll
+    for (int it = 0; it < kResolvePasses; ++it) {
+        const bool hole = (holes >> it) & 1u;
+        const uint64_t hm = __ballot(hole);
+        if (hole) {
+            const int64_t p = p0 + it * 256 + threadIdx.x;
+            hole_idx[base + wave_cnt[it * kResolveWaves + wave] + (uint32_t)__popcll(hm & lanes_below_mask())] =
+                (int32_t)p;
         }
     }
 }
@@ -199,7 +231,8 @@ void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12]
                     (unsigned)((ref.height + kSplatBlock - 1) / kSplatBlock));
     hipLaunchKernelGGL(k_warp_splat, grid, dim3(kSplatBlock * kSplatBlock), 0, s, ref, tgt, wt, ref_depth,
                        (unsigned long long *)zbuf);
-    hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, nt,
+    const int64_t per_block = (int64_t)kResolvePasses * 256;
+    hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((nt + per_block - 1) / per_block)), dim3(256), 0, s, nt,
                        (const unsigned long long *)zbuf, ref, wt, cmin, ref_depth, ref_rgb, tgt_rgb, tgt_depth, mask,
                        src_index, hole_idx, n_holes);
 }
