@@ -166,20 +166,24 @@ __device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &
 
 // ---------------------------------------------------------------------------
 // Voxel order with LDS-staged bricks (the memory-centric rendering of Sec.
-// IV-A): workgroups claim bricks of 8^3 voxels from a device counter, stage
-// the brick's 9^3 vertices x 12 feature channels in LDS (35 KB as float32),
-// and gather every sample of the brick from LDS.  Each feature vertex is then
-// read from the grid once per brick instead of by every sample near it.
+// IV-A): workgroups claim segments of up to kTileSeg samples of one brick of
+// 8^3 voxels, stage the brick's 9^3 vertices x 12 feature channels in LDS
+// (36 KB as float32) together with the segment's per-sample records (record
+// index, ray, voxel fractions and cell within the brick, 24 B per sample),
+// and then run the MLP batches from LDS.  Each feature vertex is read from
+// the grid once per segment instead of by every sample near it, and the
+// dependent loads that locate a sample (its record, its ray, the ray's
+// origin and direction) are issued by the whole workgroup at once.
 // ---------------------------------------------------------------------------
 constexpr int kFTileV = kBrick + 1;
-#ifndef CIC_TILE_SOA
-#define CIC_TILE_SOA 1
-#endif
 // Channel-major tile: channel ch of vertex v at ch * kFTileS + v.  The
 // channel stride is padded so that the four 16-lane groups of a wavefront
 // (channels 3q + c) start 16 banks apart.
 constexpr int kFTileS = 752;
-constexpr int kFTileFloats = CIC_TILE_SOA ? 12 * kFTileS : kFTileV * kFTileV * kFTileV * 12;
+constexpr int kFTileFloats = 12 * kFTileS;
+// Segment records in LDS (structure of arrays, kTileSeg entries each):
+// record index, ray, three voxel fractions, packed cell (lx | ly << 4 | lz << 8).
+constexpr int kSegWords = 6 * kTileSeg;
 
 // origin vertex of a brick (kept in registers by the callers)
 struct BrickBase {
@@ -206,28 +210,21 @@ __device__ void load_feature_tile(const GridK &g, const BrickBase base, float *t
 #pragma unroll
             for (int c = 0; c < 4; ++c) v[c] = ldv(feat, off + c);
         }
-        if (CIC_TILE_SOA) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) tile[(4 * part + c) * kFTileS + vtx] = v[c];
-        } else {
-            *(f4_t *)(tile + vtx * 12 + 4 * part) = v;
-        }
+        for (int c = 0; c < 4; ++c) tile[(4 * part + c) * kFTileS + vtx] = v[c];
     }
 }
 
-// Features 3q..3q+2 of a sample in cell i0 of the staged brick (same
-// interpolation order as the gather from the grid).
-__device__ __forceinline__ void tile_gather3(const float *tile, const BrickBase base, const int i0[3], const float fr[3],
-                                             int q, float x[3])
+// Features 3q..3q+2 of a sample in cell (lx, ly, lz) of the staged brick
+// (same interpolation order as the gather from the grid).
+__device__ __forceinline__ void tile_gather3(const float *tile, int lx, int ly, int lz, const float fr[3], int q,
+                                             float x[3])
 {
-    const int lx = i0[0] - base.x, ly = i0[1] - base.y, lz = i0[2] - base.z;
-    const int vtx = (lx * kFTileV + ly) * kFTileV + lz;
-    const int vs = CIC_TILE_SOA ? 1 : 12, cs = CIC_TILE_SOA ? kFTileS : 1;
-    const int sx = kFTileV * kFTileV * vs, sy = kFTileV * vs, sz = vs;
-    const float *t = tile + vtx * vs + 3 * q * cs;
+    const int sx = kFTileV * kFTileV, sy = kFTileV, sz = 1;
+    const float *t = tile + (lx * kFTileV + ly) * kFTileV + lz + 3 * q * kFTileS;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float *u = t + c * cs;
+        const float *u = t + c * kFTileS;
         const float v000 = u[0], v001 = u[sz], v010 = u[sy], v011 = u[sy + sz];
         const float v100 = u[sx], v101 = u[sx + sz], v110 = u[sx + sy], v111 = u[sx + sy + sz];
         const float c00 = lerpf(v000, v001, fr[2]), c01 = lerpf(v010, v011, fr[2]);
@@ -237,25 +234,27 @@ __device__ __forceinline__ void tile_gather3(const float *tile, const BrickBase 
     }
 }
 
-// Inputs of one sample from the staged brick: features from LDS, and (PE)
-// the view encoding.
-template <bool PE>
-__device__ __forceinline__ void sample_inputs_tile(const GridK &g, const RenderBufs &b, int64_t rec, int q,
-                                                   const float *tile, const BrickBase base, float x[10], uint32_t &ray)
+// The segment's per-sample records into LDS (every thread of the workgroup;
+// same voxel computation as the march, so the cell and fractions are the
+// ones the gather from the grid would use).
+__device__ void stage_segment(const GridK &g, const RenderBufs &b, uint32_t start, int n, const BrickBase base,
+                              uint32_t *seg)
 {
-    SampleRay r;
-    ray = b.rec_ray[rec];
-    load_sample_ray(b, ray, b.rec_k[rec], r);
-    int i0[3];
-    float fr[3], tk;
-    sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
-    tile_gather3(tile, base, i0, fr, q, x);
-    if (!PE) {
-#pragma unroll
-        for (int c = 3; c < 10; ++c) x[c] = 0.f;
-        return;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const uint32_t rec = b.perm[start + e];
+        SampleRay r;
+        load_sample_ray(b, b.rec_ray[rec], b.rec_k[rec], r);
+        int i0[3];
+        float fr[3], tk;
+        sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
+        seg[e] = rec;
+        seg[kTileSeg + e] = r.ray;
+        seg[2 * kTileSeg + e] = __float_as_uint(fr[0]);
+        seg[3 * kTileSeg + e] = __float_as_uint(fr[1]);
+        seg[4 * kTileSeg + e] = __float_as_uint(fr[2]);
+        seg[5 * kTileSeg + e] =
+            (uint32_t)(i0[0] - base.x) | ((uint32_t)(i0[1] - base.y) << 4) | ((uint32_t)(i0[2] - base.z) << 8);
     }
-    encode_group(r.d, q, x + 3);
 }
 
 // Claim the next segment (up to kTileSeg samples of one brick) for this
@@ -697,7 +696,8 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
     extern __shared__ float lds_raw[];
     bf8_t *frag = (bf8_t *)lds_raw;
     float *fl = lds_raw + kBfFrags * 4;
-    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;   // TILE only
+    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;    // TILE only: the brick's features
+    uint32_t *seg = (uint32_t *)(tile + kFTileFloats);   // TILE only: the segment's records
     __shared__ TileWork seg_slot;
     stage_weights_bf16(m, frag, fl);
     __syncthreads();
@@ -707,8 +707,8 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
     const int64_t total = (int64_t)b.offsets[b.n];
 
     // one batch of kBfNT tiles: samples s0 + nt*16 + j below send (TILE:
-    // of the brick staged with origin base)
-    auto batch = [&](int64_t s0, int64_t send, const BrickBase base) {
+    // positions in the staged segment)
+    auto batch = [&](int64_t s0, int64_t send) {
         bf8_t xin[kBfNT][2];
         int64_t rec[kBfNT];
         bool valid[kBfNT];
@@ -716,13 +716,19 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         for (int nt = 0; nt < kBfNT; ++nt) {
             const int64_t s = s0 + nt * 16 + j;
             valid[nt] = s < send;
-            rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
+            if (TILE) rec[nt] = valid[nt] ? (int64_t)seg[s] : 0;
+            else rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
             float x[10];
             bf8_t ev;
             if (valid[nt]) {
                 uint32_t ray;
                 if (TILE) {
-                    sample_inputs_tile<false>(g, b, rec[nt], q, tile, base, x, ray);
+                    ray = seg[kTileSeg + s];
+                    const float fr[3] = {__uint_as_float(seg[2 * kTileSeg + s]),
+                                         __uint_as_float(seg[3 * kTileSeg + s]),
+                                         __uint_as_float(seg[4 * kTileSeg + s])};
+                    const uint32_t cell = seg[5 * kTileSeg + s];
+                    tile_gather3(tile, (int)(cell & 15u), (int)((cell >> 4) & 15u), (int)(cell >> 8), fr, q, x);
                 } else {
                     sample_inputs<T, false>(g, b, rec[nt], q, x);
                     ray = b.rec_ray[rec[nt]];
@@ -814,16 +820,17 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         TileWork w;
         while (claim_segment(b, &seg_slot, w)) {
             const BrickBase base = brick_base(g, w.brick);
+            const int n = (int)(w.end - w.start);
             load_feature_tile<T>(g, base, tile);
+            stage_segment(g, b, w.start, n, base, seg);
             __syncthreads();
-            const int64_t nb = ((int64_t)w.end - w.start + kBfBatch - 1) / kBfBatch;
-            for (int64_t bi = wave; bi < nb; bi += kBfWaves)
-                batch((int64_t)w.start + bi * kBfBatch, (int64_t)w.end, base);
+            const int nb = (n + kBfBatch - 1) / kBfBatch;
+            for (int bi = wave; bi < nb; bi += kBfWaves) batch((int64_t)bi * kBfBatch, (int64_t)n);
         }
     } else {
         const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
         const BatchRange br = xcd_batches(nbatch, kBfWaves, wave);
-        for (int64_t bt = br.first; bt < br.end; bt += br.stride) batch(bt * kBfBatch, total, BrickBase{0, 0, 0});
+        for (int64_t bt = br.first; bt < br.end; bt += br.stride) batch(bt * kBfBatch, total);
     }
 }
 
@@ -856,7 +863,7 @@ static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bo
 template <typename T, bool TILE>
 static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
-    const int lds = kLdsBf16 + (TILE ? kFTileFloats * (int)sizeof(float) : 0);
+    const int lds = kLdsBf16 + (TILE ? (kFTileFloats + kSegWords) * 4 : 0);
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T, TILE>, hipFuncAttributeMaxDynamicSharedMemorySize,
