@@ -86,6 +86,9 @@ void launch_build_occupancy(const GridK &g, float thr, uint8_t *occ, hipStream_t
 int mlp_lds_bytes(int compute);
 template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
+// mlp_bf16.hip: the BF16 forward (called by launch_mlp_forward for BF16 compute)
+template <typename T>
+void launch_mlp_forward_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
 // per-ray BF16 view encoding into b.enc (BF16 compute; rays with live samples)
 void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s);
 // per-ray direction term of layer 0 into b.z0 (rays with live samples)

@@ -1,0 +1,463 @@
+// Feature Gathering + Feature Computation (Sec. II-B) with the MLP in BF16
+// on MFMA (FP32 accumulation), in ray order or, on dense grids, in voxel
+// order from LDS-staged bricks (Sec. IV-A).
+#include "mlp_common.h"
+
+namespace cic {
+
+// BF16 compute: lane group q's seven view-encoding inputs of every ray with
+// live samples, rounded to BF16 (the rounding the MLP kernel applies to its
+// inputs) and packed as 8 BF16 (last slot 0) into words 4q..4q+3 of the ray.
+__global__ __launch_bounds__(256) void k_ray_encode_bf16(RenderBufs b)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ray = t >> 2;
+    const int q = (int)(t & 3);
+    if (ray >= b.n || b.count[ray] == 0) return;
+    float d[3], x[7];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = b.rays_d[3 * ray + a];
+    encode_group(d, q, x);
+    typedef __bf16 bf8v_t __attribute__((ext_vector_type(8)));
+    bf8v_t v;
+#pragma unroll
+    for (int e = 0; e < 7; ++e) v[e] = (__bf16)x[e];
+    v[7] = (__bf16)0.0f;
+    typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+    *(u4_t *)(b.enc + ray * 16 + 4 * q) = __builtin_bit_cast(u4_t, v);
+}
+
+void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s)
+{
+    if (b.n == 0) return;
+    const int64_t threads = 4 * b.n;
+    hipLaunchKernelGGL(k_ray_encode_bf16, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, b);
+}
+
+// ---------------------------------------------------------------------------
+// Voxel order with LDS-staged bricks (the memory-centric rendering of Sec.
+// IV-A): workgroups claim segments of up to kTileSeg samples of one brick of
+// 8^3 voxels, stage the brick's 9^3 vertices x 12 feature channels in LDS
+// (36 KB as float32) together with the segment's per-sample records (record
+// index, ray, voxel fractions and cell within the brick, 24 B per sample),
+// and then run the MLP batches from LDS.  Each feature vertex is read from
+// the grid once per segment instead of by every sample near it, and the
+// dependent loads that locate a sample (its record, its ray, the ray's
+// origin and direction) are issued by the whole workgroup at once.
+// ---------------------------------------------------------------------------
+constexpr int kFTileV = kBrick + 1;
+// Channel-major tile: channel ch of vertex v at ch * kFTileS + v.  The
+// channel stride is padded so that the four 16-lane groups of a wavefront
+// (channels 3q + c) start 16 banks apart.
+constexpr int kFTileS = 752;
+constexpr int kFTileFloats = 12 * kFTileS;
+// Segment records in LDS (structure of arrays, kTileSeg entries each):
+// record index, ray, three voxel fractions, packed cell (lx | ly << 4 | lz << 8).
+constexpr int kSegWords = 6 * kTileSeg;
+
+// origin vertex of a brick (kept in registers by the callers)
+struct BrickBase {
+    int x, y, z;
+};
+__device__ __forceinline__ BrickBase brick_base(const GridK &g, int64_t brick)
+{
+    const int bz = (int)(brick % g.nb2), by = (int)((brick / g.nb2) % g.nb1);
+    const int bx = (int)(brick / ((int64_t)g.nb2 * g.nb1));
+    return BrickBase{kBrick * bx, kBrick * by, kBrick * bz};
+}
+
+template <typename T>
+__device__ void load_feature_tile(const GridK &g, const BrickBase base, float *tile)
+{
+    const T *feat = (const T *)g.features;
+    for (int e = threadIdx.x; e < kFTileV * kFTileV * kFTileV * 3; e += blockDim.x) {
+        const int vtx = e / 3, part = e - 3 * vtx;
+        const int lz = vtx % kFTileV, ly = (vtx / kFTileV) % kFTileV, lx = vtx / (kFTileV * kFTileV);
+        const int vx = base.x + lx, vy = base.y + ly, vz = base.z + lz;
+        f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+        if (vx < g.r0 && vy < g.r1 && vz < g.r2) {
+            const int64_t off = vertex_index(g, vx, vy, vz) * 12 + 4 * part;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = ldv(feat, off + c);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tile[(4 * part + c) * kFTileS + vtx] = v[c];
+    }
+}
+
+// Features 3q..3q+2 of a sample in cell (lx, ly, lz) of the staged brick
+// (same interpolation order as the gather from the grid).
+__device__ __forceinline__ void tile_gather3(const float *tile, int lx, int ly, int lz, const float fr[3], int q,
+                                             float x[3])
+{
+    const int sx = kFTileV * kFTileV, sy = kFTileV, sz = 1;
+    const float *t = tile + (lx * kFTileV + ly) * kFTileV + lz + 3 * q * kFTileS;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float *u = t + c * kFTileS;
+        const float v000 = u[0], v001 = u[sz], v010 = u[sy], v011 = u[sy + sz];
+        const float v100 = u[sx], v101 = u[sx + sz], v110 = u[sx + sy], v111 = u[sx + sy + sz];
+        const float c00 = lerpf(v000, v001, fr[2]), c01 = lerpf(v010, v011, fr[2]);
+        const float c10 = lerpf(v100, v101, fr[2]), c11 = lerpf(v110, v111, fr[2]);
+        const float c0 = lerpf(c00, c01, fr[1]), c1 = lerpf(c10, c11, fr[1]);
+        x[c] = lerpf(c0, c1, fr[0]);
+    }
+}
+
+// The segment's per-sample records into LDS (every thread of the workgroup;
+// same voxel computation as the march, so the cell and fractions are the
+// ones the gather from the grid would use).
+__device__ void stage_segment(const GridK &g, const RenderBufs &b, uint32_t start, int n, const BrickBase base,
+                              uint32_t *seg)
+{
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const uint32_t rec = b.perm[start + e];
+        SampleRay r;
+        load_sample_ray(b, b.rec_ray[rec], b.rec_k[rec], r);
+        int i0[3];
+        float fr[3], tk;
+        sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
+        seg[e] = rec;
+        seg[kTileSeg + e] = r.ray;
+        seg[2 * kTileSeg + e] = __float_as_uint(fr[0]);
+        seg[3 * kTileSeg + e] = __float_as_uint(fr[1]);
+        seg[4 * kTileSeg + e] = __float_as_uint(fr[2]);
+        seg[5 * kTileSeg + e] =
+            (uint32_t)(i0[0] - base.x) | ((uint32_t)(i0[1] - base.y) << 4) | ((uint32_t)(i0[2] - base.z) << 8);
+    }
+}
+
+// Claim the next segment (up to kTileSeg samples of one brick) for this
+// workgroup.  The segment list is split into kXcds contiguous ranges, one
+// per XCD, each drained through its own counter: the workgroups sharing an
+// L2 then work through neighbouring bricks (and the rays crossing them)
+// instead of the whole chip's in-flight window.  Thread 0 claims and
+// locates the segment and publishes it in LDS; returns false once this
+// XCD's range is exhausted (every workgroup of the XCD then ends).  Large
+// bricks are shared by several workgroups, each staging the brick's tile.
+struct TileWork {
+    int64_t brick;
+    uint32_t start, end;
+};
+__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w)
+{
+    __syncthreads();   // every wave is done with the previous segment and tile
+    if (threadIdx.x == 0) {
+        const int xcd = blockIdx.x % kXcds;
+        const uint64_t nseg = b.seg_off[b.n_bricks];
+        const uint64_t k = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, 1u);
+        TileWork t{-1, 0u, 0u};
+        if (k < nseg * (xcd + 1) / kXcds) {
+            // brick: the last index with seg_off[brick] <= k
+            int64_t lo = 0, hi = b.n_bricks;   // invariant: seg_off[lo] <= k < seg_off[hi]
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (b.seg_off[mid] <= k) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t bstart = lo == 0 ? 0u : b.brick_off[lo - 1], bend = b.brick_off[lo];
+            t.brick = lo;
+            t.start = bstart + ((uint32_t)k - b.seg_off[lo]) * (uint32_t)kTileSeg;
+            t.end = min(bend, t.start + (uint32_t)kTileSeg);
+        }
+        *slot = t;
+    }
+    __syncthreads();
+    w = *slot;
+    return w.brick >= 0;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 variant: every layer on v_mfma_f32_16x16x32_bf16 (inputs rounded to
+// BF16 with round-to-nearest-even, FP32 accumulation, FP32 bias and
+// activations).  K = 32 per instruction: lane (q, j) supplies 8 consecutive
+// reduction slots.  Layer 0 uses two K-chunks (64 slots >= 39 inputs, same
+// per-lane input assignment as the FP32 kernel: the ten values of lane group
+// q fill chunk 0 and the first two slots of chunk 1).  Layers 1 and 2 take
+// their B operand from two consecutive 16-row result tiles of the previous
+// layer: chunk c of lane group q covers rows 32c + 4q + (0..3) and
+// 32c + 16 + 4q + (0..3), and the weight fragments are laid out to match.
+// The 3-wide output layer is one zero-padded 16-row tile.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// Launch shape (measured on the 8-view workload, MLP stage): a BF16 MFMA does
+// a 16-sample tile's layer in 1/16 of the FP32 time, so each batch carries
+// little MFMA work against its dependent gather loads and its weight reads
+// from LDS; 16 wavefronts per CU (128 VGPRs each) with two tiles per batch
+// hide the loads best and read each weight fragment for 32 samples
+// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms).
+#ifndef CIC_BF_NT
+#define CIC_BF_NT 2
+#endif
+
+#ifndef CIC_BF_WAVES
+#define CIC_BF_WAVES 16
+#endif
+#ifndef CIC_BF_WGS
+#define CIC_BF_WGS 1
+#endif
+constexpr int kBfWaves = CIC_BF_WAVES;   // wavefronts per workgroup
+constexpr int kBfWgs = CIC_BF_WGS;       // workgroups per CU (each holds its own 53 KB of LDS weights)
+constexpr int kBfNT = CIC_BF_NT;         // 16-sample tiles per wavefront batch
+constexpr int kBfBatch = 16 * kBfNT;
+// LDS layout in 16-byte fragments, then floats
+constexpr int kBfW0 = 0;                           // [t 8][c 2][lane 64]
+constexpr int kBfW1 = kBfW0 + 8 * 2 * 64;          // [t 8][c 4][lane 64]
+constexpr int kBfW2 = kBfW1 + 8 * 4 * 64;          // [c 4][lane 64]
+constexpr int kBfFrags = kBfW2 + 4 * 64;
+constexpr int kBfB0 = 0, kBfB1 = 128, kBfB2 = 256, kBfFloats = 260;
+constexpr int kLdsBf16 = kBfFrags * 16 + kBfFloats * 4;
+
+// reduction index of slot e of chunk c for lane group q in layers 1 and 2
+__host__ __device__ __forceinline__ int hid_k(int c, int q, int e)
+{
+    return e < 4 ? 32 * c + 4 * q + e : 32 * c + 16 + 4 * q + (e - 4);
+}
+
+// input index of slot e of chunk c for lane group q in layer 0 (-1 = pad)
+__host__ __device__ __forceinline__ int bf_l0_input(int c, int q, int e)
+{
+    const int slot = 8 * c + e;
+    return slot < 10 ? l0_input(slot, q) : -1;
+}
+
+__device__ void stage_weights_bf16(const cic_mlp &m, bf8_t *frag, float *fl)
+{
+    const int nt = blockDim.x;
+    for (int i = threadIdx.x; i < 8 * 2 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) & 1, t = i >> 7;
+        const int row = 16 * t + (l & 15), q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int src = bf_l0_input(c, q, e);
+            v[e] = (__bf16)(src >= 0 ? m.w0[row * 39 + src] : 0.f);
+        }
+        frag[kBfW0 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 8 * 4 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) & 3, t = i >> 8;
+        const int row = 16 * t + (l & 15), q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)m.w1[row * 128 + hid_k(c, q, e)];
+        frag[kBfW1 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 4 * 64; i += nt) {
+        const int l = i & 63, c = i >> 6;
+        const int row = l & 15, q = l >> 4;
+        bf8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)(row < 3 ? m.w2[row * 128 + hid_k(c, q, e)] : 0.f);
+        frag[kBfW2 + i] = v;
+    }
+    for (int i = threadIdx.x; i < 128; i += nt) {
+        fl[kBfB0 + i] = m.b0[i];
+        fl[kBfB1 + i] = m.b1[i];
+    }
+    if (threadIdx.x < 4) fl[kBfB2 + threadIdx.x] = threadIdx.x < 3 ? m.b2[threadIdx.x] : 0.f;
+}
+
+__device__ __forceinline__ bf8_t pack_bf8(const f4_t a, const f4_t b)
+{
+    bf8_t v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = (__bf16)a[e];
+        v[4 + e] = (__bf16)b[e];
+    }
+    return v;
+}
+
+// ReLU of BF16 values as 16-bit integers: a negative BF16 (sign bit set) is
+// a negative int16, so max(bits, 0) zeroes exactly the negatives (and -0).
+// Rounding to BF16 preserves sign, so this equals rounding after the ReLU.
+typedef short s8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf8_t relu_bf8(bf8_t v)
+{
+    s8_t s = __builtin_bit_cast(s8_t, v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = s[e] > 0 ? s[e] : (short)0;
+    return __builtin_bit_cast(bf8_t, s);
+}
+
+// TILE: voxel order with the brick's features staged in LDS (dense grids).
+template <typename T, bool TILE>
+__global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
+{
+    extern __shared__ float lds_raw[];
+    bf8_t *frag = (bf8_t *)lds_raw;
+    float *fl = lds_raw + kBfFrags * 4;
+    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;    // TILE only: the brick's features
+    uint32_t *seg = (uint32_t *)(tile + kFTileFloats);   // TILE only: the segment's records
+    __shared__ TileWork seg_slot;
+    stage_weights_bf16(m, frag, fl);
+    __syncthreads();
+
+    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+    const int wave = threadIdx.x / 64;
+    const int64_t total = (int64_t)b.offsets[b.n];
+
+    // one batch of kBfNT tiles: samples s0 + nt*16 + j below send (TILE:
+    // positions in the staged segment)
+    auto batch = [&](int64_t s0, int64_t send) {
+        bf8_t xin[kBfNT][2];
+        int64_t rec[kBfNT];
+        bool valid[kBfNT];
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) {
+            const int64_t s = s0 + nt * 16 + j;
+            valid[nt] = s < send;
+            if (TILE) rec[nt] = valid[nt] ? (int64_t)seg[s] : 0;
+            else rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
+            float x[10];
+            bf8_t ev;
+            if (valid[nt]) {
+                uint32_t ray;
+                if (TILE) {
+                    ray = seg[kTileSeg + s];
+                    const float fr[3] = {__uint_as_float(seg[2 * kTileSeg + s]),
+                                         __uint_as_float(seg[3 * kTileSeg + s]),
+                                         __uint_as_float(seg[4 * kTileSeg + s])};
+                    const uint32_t cell = seg[5 * kTileSeg + s];
+                    tile_gather3(tile, (int)(cell & 15u), (int)((cell >> 4) & 15u), (int)(cell >> 8), fr, q, x);
+                } else {
+                    sample_inputs<T, false>(g, b, rec[nt], q, x);
+                    ray = b.rec_ray[rec[nt]];
+                }
+                typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+                ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)ray * 16 + 4 * q));
+            } else {
+#pragma unroll
+                for (int c = 0; c < 10; ++c) x[c] = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) ev[e] = (__bf16)0.0f;
+            }
+            // chunk 0: features 3q..3q+2 then encoding slots 0..4; chunk 1: slots 5, 6
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                xin[nt][0][e] = e < 3 ? (__bf16)x[e] : ev[e - 3];
+                xin[nt][1][e] = e < 2 ? ev[5 + e] : (__bf16)0.0f;
+            }
+
+        }
+        // layer 0
+        f4_t h1[8][kBfNT];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f4_t bias = *(const f4_t *)(fl + kBfB0 + 16 * t + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) h1[t][nt] = bias;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kBfNT; ++nt)
+                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], h1[t][nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        bf8_t hb[4][kBfNT];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) hb[c][nt] = relu_bf8(pack_bf8(h1[2 * c][nt], h1[2 * c + 1][nt]));
+        // layer 1
+        f4_t h2[8][kBfNT];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f4_t bias = *(const f4_t *)(fl + kBfB1 + 16 * t + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt) h2[t][nt] = bias;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bf8_t a = frag[kBfW1 + (t * 4 + c) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kBfNT; ++nt)
+                    h2[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][nt], h2[t][nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2 (one zero-padded tile)
+        f4_t o3[kBfNT];
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) o3[nt] = *(const f4_t *)(fl + kBfB2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bf8_t a = frag[kBfW2 + c * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < kBfNT; ++nt)
+                o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, relu_bf8(pack_bf8(h2[2 * c][nt], h2[2 * c + 1][nt])),
+                                                                 o3[nt], 0, 0, 0);
+        }
+        // lanes of group 0 hold rows 0..3 (colour channels 0..2) of their sample
+#pragma unroll
+        for (int nt = 0; nt < kBfNT; ++nt) {
+            if (valid[nt] && q == 0) {
+                float *out = b.rec_c + 3 * rec[nt];
+                out[0] = sigmoidf(o3[nt][0]);
+                out[1] = sigmoidf(o3[nt][1]);
+                out[2] = sigmoidf(o3[nt][2]);
+            }
+        }
+    };
+
+    if (TILE) {
+        TileWork w;
+        while (claim_segment(b, &seg_slot, w)) {
+            const BrickBase base = brick_base(g, w.brick);
+            const int n = (int)(w.end - w.start);
+            load_feature_tile<T>(g, base, tile);
+            stage_segment(g, b, w.start, n, base, seg);
+            __syncthreads();
+            const int nb = (n + kBfBatch - 1) / kBfBatch;
+            for (int bi = wave; bi < nb; bi += kBfWaves) batch((int64_t)bi * kBfBatch, (int64_t)n);
+        }
+    } else {
+        const int64_t nbatch = (total + kBfBatch - 1) / kBfBatch;
+        const BatchRange br = xcd_batches(nbatch, kBfWaves, wave);
+        for (int64_t bt = br.first; bt < br.end; bt += br.stride) batch(bt * kBfBatch, total);
+    }
+}
+
+#ifndef CIC_VOXEL_TILE
+#define CIC_VOXEL_TILE 1
+#endif
+template <typename T, bool TILE>
+static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+{
+    const int lds = kLdsBf16 + (TILE ? (kFTileFloats + kSegWords) * 4 : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T, TILE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
+        attr_set = true;
+    }
+    if (TILE) {
+        launch_brick_segments(b, s);
+        launch_fill_u32(b.work_ctr, 0u, kXcds, s);
+    }
+    // TILE: at least one workgroup per XCD range of segments
+    const int grid = TILE ? std::max(num_cus(b) * kBfWgs, kXcds) : num_cus(b) * kBfWgs;
+    hipLaunchKernelGGL((k_mlp_fwd_bf16<T, TILE>), dim3(grid), dim3(kBfWaves * 64), lds, s, g, m, b,
+                       voxel ? 1 : 0);
+}
+
+template <typename T>
+void launch_mlp_forward_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
+{
+    if (CIC_VOXEL_TILE && voxel && g.hlevels == 0) launch_bf16_k<T, true>(g, m, b, true, s);
+    else launch_bf16_k<T, false>(g, m, b, voxel, s);
+}
+
+template void launch_mlp_forward_bf16<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
+template void launch_mlp_forward_bf16<__half>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);
+
+}  // namespace cic

@@ -1,0 +1,109 @@
+// Device helpers shared by the FP32 and BF16 MLP kernels: the per-sample
+// inputs of layer 0 (trilinear feature gather or multi-level encoding, and
+// the view-direction encoding) and the persistent grids' size.
+#pragma once
+#include "kernels.h"
+
+namespace cic {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+// Input index (0..38, or -1 for padding) of chunk c for lane group q.
+__host__ __device__ __forceinline__ int l0_input(int c, int q)
+{
+    if (c < 3) return 3 * q + c;
+    if (c == 3) return q < 3 ? 12 + q : -1;
+    const int jj = (c - 4) >> 1, p = 3 * q + jj;
+    return ((c - 4) & 1) ? 27 + p : 15 + p;
+}
+
+__device__ __forceinline__ float pick3(int i, float a, float b, float c) { return i == 0 ? a : (i == 1 ? b : c); }
+
+// View-encoding inputs of lane group q (layer-0 chunks 3-9): direction
+// component q (q = 3 pads with 0), then sin and cos of encoding pairs
+// p = 3q..3q+2, p = 4*component + octave.
+__device__ __forceinline__ void encode_group(const float d[3], int q, float x[7])
+{
+    x[0] = q < 3 ? pick3(q, d[0], d[1], d[2]) : 0.f;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+        const int p = 3 * q + jj;
+        const float a = ldexpf(pick3(p >> 2, d[0], d[1], d[2]), p & 3);
+        float sn, cs;
+        sincosf(a, &sn, &cs);
+        x[1 + 2 * jj] = sn;
+        x[2 + 2 * jj] = cs;
+    }
+}
+
+// The ray data a sample's gather needs: its ray, sample index, interval
+// start and step, origin and direction.
+struct SampleRay {
+    uint32_t ray;
+    int k;
+    float tn, delta;
+    float o[3], d[3];
+};
+
+__device__ __forceinline__ void load_sample_ray(const RenderBufs &b, uint32_t ray, int k, SampleRay &r)
+{
+    r.ray = ray;
+    r.k = k;
+    const RayInfo inf = b.info[ray];
+    r.tn = inf.tn;
+    r.delta = inf.delta;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = b.rays_o[3 * (int64_t)ray + a];
+        r.d[a] = b.rays_d[3 * (int64_t)ray + a];
+    }
+}
+
+// Layer-0 inputs of one sample for this lane's group q (PE = false: only
+// the three feature channels; the direction terms come from a per-ray
+// table).
+template <typename T, bool PE = true>
+__device__ __forceinline__ void sample_inputs_from(const GridK &g, const SampleRay &r, int q, float x[10])
+{
+    if (g.hlevels) {
+        // multi-level encoding: lane group q gathers level q
+        const float tk = sample_t(r.tn, r.delta, r.k);
+        float xp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xp[a] = r.o[a] + tk * r.d[a];
+        hash_level3<T>(g, q, xp, x);
+    } else {
+        int i0[3];
+        float fr[3], tk;
+        sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
+        const T *feat = (const T *)g.features;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+    }
+    if (!PE) {
+#pragma unroll
+        for (int c = 3; c < 10; ++c) x[c] = 0.f;
+        return;
+    }
+    encode_group(r.d, q, x + 3);
+}
+
+template <typename T, bool PE = true>
+__device__ __forceinline__ void sample_inputs(const GridK &g, const RenderBufs &b, int64_t rec, int q, float x[10])
+{
+    SampleRay r;
+    load_sample_ray(b, b.rec_ray[rec], b.rec_k[rec], r);
+    sample_inputs_from<T, PE>(g, r, q, x);
+}
+
+inline int num_cus(const RenderBufs &b)
+{
+    if (b.grid_cus > 0) return b.grid_cus;
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 256;
+}
+
+}  // namespace cic
