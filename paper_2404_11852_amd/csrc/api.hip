@@ -270,6 +270,7 @@ void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &
     bb.partials = cv.take<float>((int64_t)kWgBlocks * kPartialFloats);
     bb.df_sorted = kBwdVoxel ? cv.take<float>(12 * ns) : nullptr;
     bb.rec_draw = kBwdVoxel ? cv.take<float>(ns) : nullptr;
+    bb.seg_tiles = kBwdVoxel ? cv.take<float>(fg_max_segments(b.n_bricks, ns) * kFgTileFloats) : nullptr;
 }
 
 size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)

@@ -292,28 +292,72 @@ static int num_cus_b()
     return n > 0 ? n : 256;
 }
 
-// Feature and density gradients, one workgroup per brick of 8^3 voxels: the
-// brick's samples (contiguous in brick order) add their trilinear shares
-// into a 9x9x9-vertex tile of 13 channels (12 features, raw density) in LDS,
-// then the tile is added to the gradient grids with one global atomic per
-// nonzero entry, consecutive entries on consecutive addresses (vertices on a
-// brick face are shared with the neighbour brick, hence atomics).
+// Feature and density gradients in two steps, without atomics on floats.
+// The brick-ordered samples are cut into segments of at most kFgSeg samples
+// of one brick (a brick crossed by many rays gets several segments, which
+// keeps the workgroups' loads even).  k_fgrad_seg: one workgroup per
+// segment stages its samples (voxel fractions and the 13 gradient channels:
+// 12 features, raw density) in LDS, counting-sorts them by cell of the brick
+// (two integer LDS atomics per sample), and then each thread sums, for its
+// vertices of the brick's 9x9x9-vertex tile, the trilinear shares of the
+// samples in the up-to-8 cells around the vertex, and stores the tile row
+// into the segment's slot.  k_fgrad_gather: one workgroup per brick over the
+// vertices it owns (its 8^3 lower corner block, and the grid's last vertex
+// layer for the last brick of an axis); a vertex on a brick's lower face also
+// lies in the lower neighbours' tiles, so each vertex adds the slots of every
+// segment of the bricks containing it, in ascending brick and segment order,
+// to the gradient grids.
 constexpr int kTileV = kBrick + 1;
 constexpr int kTileCh = 13;
 constexpr int kTileFloats = kTileV * kTileV * kTileV * kTileCh;
+constexpr int kCells = kBrick * kBrick * kBrick;
+static_assert(kTileFloats == kFgTileFloats, "brick tile size");
 
-__global__ __launch_bounds__(256) void k_fgrad_brick(GridK g, RenderBufs b, BackwardBufs bb)
+// Exclusive scan of cnt[0..kCells) in place (256 threads, kCells = 2 x 256);
+// cur receives a copy (the scatter's cursors).
+__device__ void cell_scan(int *cnt, int *cur, int *tmp)
 {
-    __shared__ float tile[kTileFloats];
-    const int64_t brick = blockIdx.x;
-    const uint32_t start = brick == 0 ? 0u : b.brick_off[brick - 1];
-    const uint32_t end = b.brick_off[brick];
-    if (start >= end) return;
-    for (int e = threadIdx.x; e < kTileFloats; e += blockDim.x) tile[e] = 0.f;
+    const int t = threadIdx.x;
+    const int a = cnt[2 * t], c = cnt[2 * t + 1];
+    tmp[t] = a + c;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int v = t >= d ? tmp[t - d] : 0;
+        __syncthreads();
+        tmp[t] += v;
+        __syncthreads();
+    }
+    const int excl = tmp[t] - (a + c);
+    cnt[2 * t] = cur[2 * t] = excl;
+    cnt[2 * t + 1] = cur[2 * t + 1] = excl + a;
+}
+
+__global__ __launch_bounds__(256) void k_fgrad_seg(GridK g, RenderBufs b, BackwardBufs bb)
+{
+    static_assert(kCells == 512, "cell_scan assumes 512 cells and 256 threads");
+    __shared__ float sfr[3][kFgSeg];
+    __shared__ float sv[kTileCh][kFgSeg];
+    __shared__ uint16_t scell[kFgSeg];
+    __shared__ uint16_t order[kFgSeg];
+    __shared__ int cnt[kCells + 1], cur[kCells], tmp[256];
+    const uint32_t k = blockIdx.x;
+    if (k >= b.seg_off[b.n_bricks]) return;   // uniform per block
+    // brick: the last index with seg_off[brick] <= k
+    int64_t lo = 0, hi = b.n_bricks;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (b.seg_off[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    const int64_t brick = lo;
+    const uint32_t start = (brick == 0 ? 0u : b.brick_off[brick - 1]) + (k - b.seg_off[brick]) * (uint32_t)kFgSeg;
+    const int n = (int)(min(b.brick_off[brick], start + (uint32_t)kFgSeg) - start);
+    for (int c = threadIdx.x; c <= kCells; c += blockDim.x) cnt[c] = 0;
     __syncthreads();
     const int bz = (int)(brick % g.nb2), by = (int)((brick / g.nb2) % g.nb1), bx = (int)(brick / ((int64_t)g.nb2 * g.nb1));
     const int base[3] = {kBrick * bx, kBrick * by, kBrick * bz};
-    for (uint32_t s = start + threadIdx.x; s < end; s += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const uint32_t s = start + (uint32_t)e;
         const uint32_t rec = b.perm[s];
         const uint32_t ray = b.rec_ray[rec];
         const RayInfo inf = b.info[ray];
@@ -326,40 +370,121 @@ __global__ __launch_bounds__(256) void k_fgrad_brick(GridK g, RenderBufs b, Back
         int i0[3];
         float fr[3], tk;
         sample_voxel(o, d, inf.tn, inf.delta, b.rec_k[rec], g, i0, fr, tk);
-        const float wx[2] = {1.f - fr[0], fr[0]}, wy[2] = {1.f - fr[1], fr[1]}, wz[2] = {1.f - fr[2], fr[2]};
-        const int lx = i0[0] - base[0], ly = i0[1] - base[1], lz = i0[2] - base[2];
+        const int cell = ((i0[0] - base[0]) * kBrick + (i0[1] - base[1])) * kBrick + (i0[2] - base[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sfr[a][e] = fr[a];
         const float *df = bb.df_sorted + (int64_t)s * 12;
-        float v[kTileCh];
 #pragma unroll
-        for (int f = 0; f < 12; ++f) v[f] = df[f];
-        v[12] = bb.rec_draw[rec];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-            const float w = wx[dx] * wy[dy] * wz[dz];
-            float *t = tile + (((lx + dx) * kTileV + (ly + dy)) * kTileV + (lz + dz)) * kTileCh;
-#pragma unroll
-            for (int f = 0; f < kTileCh; ++f) atomicAdd(t + f, w * v[f]);
-        }
+        for (int f = 0; f < 12; ++f) sv[f][e] = df[f];
+        sv[12][e] = bb.rec_draw[rec];
+        scell[e] = (uint16_t)cell;
+        atomicAdd(&cnt[cell], 1);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTileFloats; e += blockDim.x) {
-        const float val = tile[e];
-        if (val == 0.f) continue;
-        const int f = e % kTileCh, vtx = e / kTileCh;
-        const int vz = base[2] + vtx % kTileV, vy = base[1] + (vtx / kTileV) % kTileV, vx = base[0] + vtx / (kTileV * kTileV);
-        if (vx < g.r0 && vy < g.r1 && vz < g.r2) {
-            const int64_t vi = vertex_index(g, vx, vy, vz);
-            if (f < 12) atomicAdd(bb.d_features + vi * 12 + f, val);
-            else atomicAdd(bb.d_density + vi, val);
+    cell_scan(cnt, cur, tmp);
+    if (threadIdx.x == 0) cnt[kCells] = n;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) order[atomicAdd(&cur[scell[e]], 1)] = (uint16_t)e;
+    __syncthreads();
+    // each tile vertex sums the shares of the samples in its up-to-8 cells
+    float *slot = bb.seg_tiles + (int64_t)k * kTileFloats;
+    for (int vtx = threadIdx.x; vtx < kTileV * kTileV * kTileV; vtx += blockDim.x) {
+        const int vz = vtx % kTileV, vy = (vtx / kTileV) % kTileV, vx = vtx / (kTileV * kTileV);
+        float acc[kTileCh];
+#pragma unroll
+        for (int f = 0; f < kTileCh; ++f) acc[f] = 0.f;
+        for (int cx = max(vx - 1, 0); cx <= min(vx, kBrick - 1); ++cx)
+            for (int cy = max(vy - 1, 0); cy <= min(vy, kBrick - 1); ++cy)
+                for (int cz = max(vz - 1, 0); cz <= min(vz, kBrick - 1); ++cz) {
+                    const int c = (cx * kBrick + cy) * kBrick + cz;
+                    for (int p = cnt[c]; p < cnt[c + 1]; ++p) {
+                        const int e = order[p];
+                        // the vertex is the cell's lower corner along an axis (weight 1 - fr) or its upper one (fr)
+                        const float wx = cx == vx ? 1.f - sfr[0][e] : sfr[0][e];
+                        const float wy = cy == vy ? 1.f - sfr[1][e] : sfr[1][e];
+                        const float wz = cz == vz ? 1.f - sfr[2][e] : sfr[2][e];
+                        const float w = wx * wy * wz;
+#pragma unroll
+                        for (int f = 0; f < kTileCh; ++f) acc[f] = fmaf(w, sv[f][e], acc[f]);
+                    }
+                }
+#pragma unroll
+        for (int f = 0; f < kTileCh; ++f) slot[vtx * kTileCh + f] = acc[f];
+    }
+}
+
+// Bricks along one axis whose tiles contain vertex coordinate x (nb bricks).
+__device__ __forceinline__ void tile_bricks(int x, int nb, int &lo, int &hi)
+{
+    hi = min(x / kBrick, nb - 1);
+    lo = (x % kBrick == 0 && x > 0) ? x / kBrick - 1 : x / kBrick;
+    lo = min(lo, hi);
+}
+
+__global__ __launch_bounds__(256) void k_fgrad_gather(GridK g, int nb0, RenderBufs b, BackwardBufs bb)
+{
+    const int64_t brick = blockIdx.x;
+    const int nb1 = g.nb1, nb2 = g.nb2;
+    const int bz = (int)(brick % nb2), by = (int)((brick / nb2) % nb1), bx = (int)(brick / ((int64_t)nb2 * nb1));
+    // nothing to add unless this brick or a lower neighbour has samples (uniform per block)
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int x = bx - ((c >> 2) & 1), y = by - ((c >> 1) & 1), z = bz - (c & 1);
+        if (x >= 0 && y >= 0 && z >= 0) {
+            const int64_t nbk = ((int64_t)x * nb1 + y) * nb2 + z;
+            any = any || b.seg_off[nbk + 1] > b.seg_off[nbk];
         }
+    }
+    if (!any) return;
+    const int rr[3] = {g.r0, g.r1, g.r2}, nbs[3] = {nb0, nb1, nb2}, bc[3] = {bx, by, bz};
+    int lo[3], cnt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = kBrick * bc[a];
+        const int hi = bc[a] == nbs[a] - 1 ? rr[a] - 1 : lo[a] + kBrick - 1;
+        cnt[a] = hi - lo[a] + 1;
+    }
+    const int n = cnt[0] * cnt[1] * cnt[2];
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int z = lo[2] + e % cnt[2], y = lo[1] + (e / cnt[2]) % cnt[1], x = lo[0] + e / (cnt[2] * cnt[1]);
+        int xl, xh, yl, yh, zl, zh;
+        tile_bricks(x, nb0, xl, xh);
+        tile_bricks(y, nb1, yl, yh);
+        tile_bricks(z, nb2, zl, zh);
+        float acc[kTileCh];
+#pragma unroll
+        for (int f = 0; f < kTileCh; ++f) acc[f] = 0.f;
+        bool hit = false;
+        for (int cx = xl; cx <= xh; ++cx)
+            for (int cy = yl; cy <= yh; ++cy)
+                for (int cz = zl; cz <= zh; ++cz) {
+                    const int64_t cb = ((int64_t)cx * nb1 + cy) * nb2 + cz;
+                    const uint32_t k0 = b.seg_off[cb], k1 = b.seg_off[cb + 1];
+                    const int loc = ((x - kBrick * cx) * kTileV + (y - kBrick * cy)) * kTileV + (z - kBrick * cz);
+                    for (uint32_t k = k0; k < k1; ++k) {
+                        hit = true;
+                        const float *t = bb.seg_tiles + (int64_t)k * kTileFloats + loc * kTileCh;
+#pragma unroll
+                        for (int f = 0; f < kTileCh; ++f) acc[f] += t[f];
+                    }
+                }
+        if (!hit) continue;
+        const int64_t vi = vertex_index(g, x, y, z);
+#pragma unroll
+        for (int f = 0; f < 12; ++f) bb.d_features[vi * 12 + f] += acc[f];
+        bb.d_density[vi] += acc[12];
     }
 }
 
 void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
     if (b.n_bricks == 0) return;
-    hipLaunchKernelGGL(k_fgrad_brick, dim3((unsigned)b.n_bricks), dim3(256), 0, s, g, b, bb);
+    launch_brick_segments(b, kFgSeg, s);
+    const int64_t max_seg = fg_max_segments(b.n_bricks, b.n * (int64_t)b.n_samples);
+    hipLaunchKernelGGL(k_fgrad_seg, dim3((unsigned)max_seg), dim3(256), 0, s, g, b, bb);
+    const int nb0 = (int)(b.n_bricks / ((int64_t)g.nb1 * g.nb2));
+    hipLaunchKernelGGL(k_fgrad_gather, dim3((unsigned)b.n_bricks), dim3(256), 0, s, g, nb0, b, bb);
 }
 
 void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
@@ -463,12 +588,16 @@ __global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, 
 }
 
 // Sum the per-block partials in block order and add into the gradients.
-__global__ __launch_bounds__(256) void k_wgrad_apply(const float *partials, int nblk, BackwardBufs bb)
+// Sum of the per-block partials of every weight-gradient entry, added to the
+// gradient.  A block takes 64 consecutive outputs; its 16 groups of 64
+// threads sum contiguous ranges of blocks (coalesced over the outputs), and
+// the group sums are added in group order: a fixed order, so the result is
+// deterministic.
+constexpr int kApplyOut = 64, kApplyGroups = 16;
+
+__device__ __forceinline__ bool wgrad_entry(int e, int &src, float *&dst, const BackwardBufs &bb)
 {
     constexpr int P1 = 128 * 48, P2 = P1 + 128 * 128, P3 = P2 + 16 * 128, P4 = P3 + 128 * 16;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    int src;
-    float *dst;
     if (e < 128 * 39) {
         src = (e / 39) * 48 + e % 39;
         dst = bb.d_w0 + e;
@@ -493,11 +622,33 @@ __global__ __launch_bounds__(256) void k_wgrad_apply(const float *partials, int 
         src = P4 + ch * 16 + 7;
         dst = bb.d_b2 + ch;
     } else {
-        return;
+        return false;
     }
+    return true;
+}
+
+__global__ __launch_bounds__(kApplyOut * kApplyGroups) void k_wgrad_apply(const float *partials, int nblk,
+                                                                          BackwardBufs bb)
+{
+    __shared__ float part[kApplyGroups][kApplyOut];
+    const int o = threadIdx.x % kApplyOut, grp = threadIdx.x / kApplyOut;
+    const int e = blockIdx.x * kApplyOut + o;
+    int src = 0;
+    float *dst = nullptr;
+    const bool ok = wgrad_entry(e, src, dst, bb);
+    const int per = (nblk + kApplyGroups - 1) / kApplyGroups;
+    const int b0 = grp * per, b1 = min(nblk, b0 + per);
     float sum = 0.f;
-    for (int blk = 0; blk < nblk; ++blk) sum += partials[(int64_t)blk * kPartialFloats + src];
-    *dst += sum;
+    if (ok)
+        for (int blk = b0; blk < b1; ++blk) sum += partials[(int64_t)blk * kPartialFloats + src];
+    part[grp][o] = sum;
+    __syncthreads();
+    if (grp == 0 && ok) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < kApplyGroups; ++k) t += part[k][o];
+        *dst += t;
+    }
 }
 
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
@@ -508,8 +659,8 @@ void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_
     hipLaunchKernelGGL(k_wgrad, dim3(kWgBlocks), dim3(kWgWaves * 64), 0, s, (const float *)b.stage, b.offsets + b.n,
                        bb.partials, slab);
     const int n_out = 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3;
-    hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + 255) / 256), dim3(256), 0, s, (const float *)bb.partials,
-                       kWgBlocks, bb);
+    hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + kApplyOut - 1) / kApplyOut), dim3(kApplyOut * kApplyGroups), 0, s,
+                       (const float *)bb.partials, kWgBlocks, bb);
 }
 
 }  // namespace cic

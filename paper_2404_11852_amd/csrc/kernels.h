@@ -67,9 +67,13 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 
-// segments of at most kTileSeg samples per brick for the LDS-tile MLP kernels
+// segments of at most kTileSeg samples per brick for the LDS-tile MLP kernels,
+// and of at most kFgSeg samples for the brick-tile gradient accumulation
 constexpr int kTileSeg = 2048;
-void launch_brick_segments(const RenderBufs &b, hipStream_t s);
+constexpr int kFgSeg = 512;
+// seg_off[k] = first segment of brick k (exclusive scan of ceil(count / seg));
+// seg_off[n_bricks] = the number of segments
+void launch_brick_segments(const RenderBufs &b, int seg, hipStream_t s);
 
 // upsample.hip
 void launch_upsample_bilinear(const float *lo, int w, int h, float *out, int W, int H, int s, hipStream_t st);
@@ -111,7 +115,10 @@ struct BackwardBufs {
     float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
     float *df_sorted;      // [n*N][12] feature gradient per sample in brick order (brick-tile mode), else null
     float *rec_draw;       // [n*N] raw-density gradient per live sample (brick-tile mode), else null
+    float *seg_tiles;      // [max segments][kFgTileFloats] each segment's accumulated gradient tile (brick-tile mode)
 };
+// 9^3 vertices x (12 feature + 1 density) gradient channels per brick tile
+constexpr int kFgTileFloats = (kBrick + 1) * (kBrick + 1) * (kBrick + 1) * 13;
 constexpr int kWgBlocks = 1024;
 // per-block partial products: dp0^T[x|1] (128x48), dp1^T h1 (128x128),
 // dl^T h2 (16x128), dp1^T ones (128x16), dl^T ones (16x16)
@@ -121,7 +128,10 @@ void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs 
 void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
                          hipStream_t s);
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
-// brick-tile accumulation of the feature gradients written by the MLP backward
+// brick-tile accumulation of the feature and density gradients written by the
+// MLP backward and the compositing adjoint, then their addition to the grids
 void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
+// most segments of kFgSeg samples a pass of ns sample slots can have
+inline int64_t fg_max_segments(int64_t n_bricks, int64_t ns) { return n_bricks + ns / kFgSeg + 1; }
 
 }  // namespace cic

@@ -441,7 +441,7 @@ static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b,
         attr_set = true;
     }
     if (TILE) {
-        launch_brick_segments(b, s);
+        launch_brick_segments(b, kTileSeg, s);
         launch_fill_u32(b.work_ctr, 0u, kXcds, s);
     }
     // TILE: at least one workgroup per XCD range of segments

@@ -335,18 +335,19 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
 }
 // Segments per brick (ceil(count / kTileSeg)) into seg_off, then their
 // exclusive scan: brick k owns segments seg_off[k] .. seg_off[k+1]-1.
-__global__ void k_brick_segments(RenderBufs b)
+__global__ void k_brick_segments(RenderBufs b, uint32_t seg)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= b.n_bricks) return;
     const uint32_t start = k == 0 ? 0u : b.brick_off[k - 1], end = b.brick_off[k];
-    b.seg_off[k] = (end - start + (uint32_t)kTileSeg - 1u) / (uint32_t)kTileSeg;
+    b.seg_off[k] = (end - start + seg - 1u) / seg;
 }
 
-void launch_brick_segments(const RenderBufs &b, hipStream_t s)
+void launch_brick_segments(const RenderBufs &b, int seg, hipStream_t s)
 {
     if (b.n_bricks > 0)
-        hipLaunchKernelGGL(k_brick_segments, dim3((unsigned)((b.n_bricks + 255) / 256)), dim3(256), 0, s, b);
+        hipLaunchKernelGGL(k_brick_segments, dim3((unsigned)((b.n_bricks + 255) / 256)), dim3(256), 0, s, b,
+                           (uint32_t)seg);
     launch_exclusive_scan(b.seg_off, b.seg_off, b.brick_tmp, b.n_bricks, s);   // also writes the total
 }
 

@@ -1,6 +1,7 @@
 """GPU adjoint (render_backward) against the oracle's float64 adjoint: per
-tensor, ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-4, on a small case and on
-the full training-step size (160^3 grids, 8192 rays x 256 samples)."""
+tensor, ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-4, on a small case, on a
+pass of several chunks with densely sampled bricks, and on the full
+training-step size (160^3 grids, 8192 rays x 256 samples)."""
 import numpy as np
 import pytest
 import torch
@@ -60,6 +61,29 @@ def test_backward_small_matches_oracle():
     o, d = synth.random_rays(700, seed=9)
     gt = np.random.default_rng(1).uniform(0, 1, (700, 3))
     g, og = _run(p, 64, 0.0, o, d, gt, with_depth=True)
+    for k in NAMES:
+        r = _rel(to_np(g[k]), og[k])
+        print("%s rel %.2e" % (k, r))
+        assert r <= 1e-4, (k, r)
+
+
+def test_backward_multichunk_dense_bricks():
+    """18000 parallel rays through a narrow beam of a 24^3 grid: three chunks
+    of the pass (8192 rays each at most), gradients accumulated across them,
+    and a few bricks holding thousands of samples each, so every such brick
+    is cut into several segments whose tiles the vertex gather adds up."""
+    print_case("backward 24^3, 18000 beam rays, N=128")
+    p = Pair(24, seed=6, mlp_seed=8, bias_std=0.1)
+    n = 18000
+    rng = np.random.default_rng(21)
+    o = np.zeros((n, 3), np.float32)
+    o[:, 0] = rng.uniform(-0.3, 0.3, n)
+    o[:, 1] = rng.uniform(-0.3, 0.3, n)
+    o[:, 2] = -3.0
+    d = np.tile(np.array([[0.05, -0.03, 1.0]], np.float32), (n, 1))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    gt = rng.uniform(0, 1, (n, 3))
+    g, og = _run(p, 128, 0.0, o, d, gt, with_depth=True)
     for k in NAMES:
         r = _rel(to_np(g[k]), og[k])
         print("%s rel %.2e" % (k, r))
