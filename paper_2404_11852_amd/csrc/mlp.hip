@@ -144,11 +144,12 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
     const BatchRange br = xcd_batches(nbatch, kMlpWaves, wave);
     for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
         // Wave priority (within this kernel's wavefronts on a SIMD): low
-        // while gathering the batch's inputs, high from layer 0 to the
-        // output.  Fair sharing of the matrix unit otherwise lets the four
-        // wavefronts of a SIMD finish their MFMA phases together and then
-        // wait on their gathers together (measured: 16.68 -> 16.24 ms per
-        // 800x800 frame).
+        // while gathering the batch's inputs, raised at each layer so that
+        // the wavefront furthest through its batch wins the matrix unit.
+        // Fair sharing otherwise lets the four wavefronts of a SIMD finish
+        // their MFMA phases together and then wait on their gathers together
+        // (measured per 800x800 frame: 16.68 ms without priorities, 16.37 ms
+        // with one raise at layer 0, 16.23-16.30 ms raising per layer).
         __builtin_amdgcn_s_setprio(0);
         float x[kNT][10];
         uint32_t rec[kNT];
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
         }
 
         // layer 1: 128 -> 128
+        __builtin_amdgcn_s_setprio(2);
         f4_t h2[8][kNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -291,6 +293,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
                     }
         }
         // layer 2: 128 -> 3 on the vector ALUs, then sigmoid
+        __builtin_amdgcn_s_setprio(3);
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
             float p0 = 0.f, p1 = 0.f, p2 = 0.f;
