@@ -266,6 +266,7 @@ void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &
     b.slot_t = cv.take<float>(ns);
     b.rec_t = cv.take<float>(ns);
     b.stage = cv.take<float>(ns * kStageStride);
+    b.stage_mask = cv.take<uint32_t>(ns * 8);
     bb.rec_dc = cv.take<float>(3 * ns);
     bb.partials = cv.take<float>((int64_t)kWgBlocks * kPartialFloats);
     bb.df_sorted = kBwdVoxel ? cv.take<float>(12 * ns) : nullptr;

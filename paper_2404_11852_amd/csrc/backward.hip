@@ -170,13 +170,14 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
         int64_t rec[kBNT];
         bool valid[kBNT];
         f4_t dp1[8][kBNT];
-        f4_t h1m[8][kBNT];   // h1 > 0 masks as values
+        uint32_t h1m[kBNT];   // ReLU mask of h1: bit 4t + r for row 16t + 4q + r
 #pragma unroll
         for (int nt = 0; nt < kBNT; ++nt) {
             const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
             valid[nt] = s < total;
             rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
-            const float *row = b.stage + rec[nt] * kStageStride;
+            const uint32_t h2m = valid[nt] ? b.stage_mask[rec[nt] * 8 + 4 + q] : 0u;
+            h1m[nt] = valid[nt] ? b.stage_mask[rec[nt] * 8 + q] : 0u;
             float dl[3] = {0.f, 0.f, 0.f};
             if (valid[nt]) {
 #pragma unroll
@@ -187,13 +188,11 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
             }
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const f4_t h2 = valid[nt] ? *(const f4_t *)(row + kStH2 + 16 * t + 4 * q) : f4_t{0.f, 0.f, 0.f, 0.f};
-                h1m[t][nt] = valid[nt] ? *(const f4_t *)(row + kStH1 + 16 * t + 4 * q) : f4_t{0.f, 0.f, 0.f, 0.f};
                 const f4_t wa = w2l[(q * 3 + 0) * 8 + t], wb = w2l[(q * 3 + 1) * 8 + t], wc = w2l[(q * 3 + 2) * 8 + t];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float v = fmaf(wa[r], dl[0], fmaf(wb[r], dl[1], wc[r] * dl[2]));
-                    dp1[t][nt][r] = h2[r] > 0.f ? v : 0.f;
+                    dp1[t][nt][r] = ((h2m >> (4 * t + r)) & 1u) ? v : 0.f;
                 }
             }
             if (valid[nt]) {
@@ -233,7 +232,7 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
 #pragma unroll
             for (int nt = 0; nt < kBNT; ++nt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dp0[ti][nt][r] = h1m[ti][nt][r] > 0.f ? dp0[ti][nt][r] : 0.f;
+                for (int r = 0; r < 4; ++r) dp0[ti][nt][r] = ((h1m[nt] >> (4 * ti + r)) & 1u) ? dp0[ti][nt][r] : 0.f;
 #pragma unroll
         for (int nt = 0; nt < kBNT; ++nt)
             if (valid[nt]) {

@@ -230,9 +230,16 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
                 if (valid[nt])
+                {
+                    uint32_t mk = 0u;
 #pragma unroll
-                    for (int t = 0; t < 8; ++t)
+                    for (int t = 0; t < 8; ++t) {
                         *(f4_t *)(b.stage + (int64_t)rec[nt] * kStageStride + kStH1 + 16 * t + 4 * q) = h1[t][nt];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) mk |= (h1[t][nt][r] > 0.f ? 1u : 0u) << (4 * t + r);
+                    }
+                    b.stage_mask[(int64_t)rec[nt] * 8 + q] = mk;
+                }
         }
 
         // layer 1: 128 -> 128
@@ -284,13 +291,20 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
                 if (valid[nt])
+                {
+                    uint32_t mk = 0u;
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         f4_t v = h2[t][nt];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) v[r] = relu_bits(v[r]);
+                        for (int r = 0; r < 4; ++r) {
+                            v[r] = relu_bits(v[r]);
+                            mk |= (v[r] > 0.f ? 1u : 0u) << (4 * t + r);
+                        }
                         *(f4_t *)(b.stage + (int64_t)rec[nt] * kStageStride + kStH2 + 16 * t + 4 * q) = v;
                     }
+                    b.stage_mask[(int64_t)rec[nt] * 8 + 4 + q] = mk;
+                }
         }
         // layer 2: 128 -> 3 on the vector ALUs, then sigmoid
         __builtin_amdgcn_s_setprio(3);
