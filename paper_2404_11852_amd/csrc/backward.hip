@@ -552,14 +552,29 @@ __global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, 
 #pragma unroll
     for (int i = 0; i < kWgTPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
     constexpr int kF4Row = kStageStride / 4;
-    for (int64_t sb = s0; sb < s1; sb += kWgStep) {
-        for (int e = threadIdx.x; e < kWgStep * kF4Row; e += kWgWaves * 64) {
+    // The rows of the next step are loaded into registers while this step's
+    // MFMAs run, then written to LDS (one step of software pipelining).
+    constexpr int kThreads = kWgWaves * 64;
+    constexpr int kPer = (kWgStep * kF4Row + kThreads - 1) / kThreads;
+    f4_t pre[kPer];
+    auto load_step = [&](int64_t sb) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kThreads;
             const int r = e / kF4Row, c4 = e % kF4Row;
-            const f4_t v = (sb + r < s1) ? *(const f4_t *)(stage + (sb + r) * kStageStride + 4 * c4)
-                                         : f4_t{0.f, 0.f, 0.f, 0.f};
-            *(f4_t *)(rows + r * kWgRow + 4 * c4) = v;
+            pre[i] = (e < kWgStep * kF4Row && sb + r < s1) ? *(const f4_t *)(stage + (sb + r) * kStageStride + 4 * c4)
+                                                            : f4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    load_step(s0);
+    for (int64_t sb = s0; sb < s1; sb += kWgStep) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < kWgStep * kF4Row) *(f4_t *)(rows + (e / kF4Row) * kWgRow + 4 * (e % kF4Row)) = pre[i];
         }
         __syncthreads();
+        if (sb + kWgStep < s1) load_step(sb + kWgStep);
 #pragma unroll
         for (int kk = 0; kk < kWgStep; kk += 4) {
             const float *rr = rows + (kk + (lane >> 4)) * kWgRow + (lane & 15);
