@@ -165,8 +165,12 @@ int generate_rays(const cic_camera *cam, int64_t n, const int64_t *pix,
  * T_stop is that T_k.  Skipped (unoccupied) voxels contribute sigma = 0.
  * Missed rays give rgb = bg, depth_t = 0, acc = 0.
  * opts->order = CIC_ORDER_VOXEL evaluates the MLP stage in voxel-bucket
- * order (the memory-centric ordering of Sec. IV-A); results are identical to
- * ray order.
+ * order (the memory-centric ordering of Sec. IV-A; with BF16 compute on a
+ * dense grid each brick's features are staged once in on-chip memory).
+ * Opacity and depth equal ray order's bit for bit; colours do too with BF16
+ * compute, and within float32 rounding with FP32 compute (ray order adds the
+ * view-direction term of layer 0 from a per-ray table, voxel order per
+ * sample).
  * rgb [n][3], depth_t [n], acc [n]: device float32.  n_eval (device int64,
  * nullable) is increased by the number of samples that went through the MLP. */
 int render_rays(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
