@@ -80,6 +80,11 @@ def camera(W, H, pose):
 # common.h + kernels.h).
 MLP_TRAFFIC_BYTES = 2.507e9 + 0.718e9
 MLP_TRAFFIC_SRC = "4c369ef47041c23f"
+# L2 hit rate of the same launch (TCC_HIT / (TCC_HIT + TCC_MISS)), same passes
+MLP_L2_HIT = 0.854
+# feature bytes a sample's gather requests from the grid in the MLP kernel:
+# 8 vertices x 12 channels x 4 B (the density is gathered by the march)
+GATHER_BYTES_PER_SAMPLE = 8 * 12 * 4
 
 
 def mlp_traffic():
@@ -92,6 +97,38 @@ def mlp_traffic():
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return MLP_TRAFFIC_BYTES if h.hexdigest()[:16] == MLP_TRAFFIC_SRC else None
+
+
+def measure_peaks():
+    """On-box check of the published peaks the fractions use: a 2 GiB
+    device-to-device copy (read + write bytes per second) and an 8192^3
+    float32 matrix product through torch."""
+    import torch
+    out = {}
+    src = torch.empty(1 << 29, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        dst.copy_(src)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    out["copy_GBs"] = 5 * 2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    m = torch.randn(8192, 8192, device="cuda:0")
+    n = torch.randn(8192, 8192, device="cuda:0")
+    for _ in range(2):
+        torch.mm(m, n)
+    a.record()
+    for _ in range(5):
+        torch.mm(m, n)
+    b.record()
+    torch.cuda.synchronize()
+    out["fp32_gemm_TFs"] = 5 * 2 * 8192 ** 3 / (a.elapsed_time(b) * 1e-3) / 1e12
+    out["published"] = {"hbm_GBs": PEAK_HBM_GBS, "fp32_mfma_TFs": PEAK_FP32_TFLOPS, "bf16_mfma_TFs": 2500.0}
+    return out
 
 
 def timed_frames(model, opts, cam, steps, warmup):
@@ -472,8 +509,31 @@ def cpu_baseline(scene, target_s=12.0):
         _, _, _, diag = oracle.render_pixels(om, op, oc, pix)
         dt = time.perf_counter() - t0
     ns = int(diag["n_eval"].sum())
-    return {"value": ns / dt, "unit": "samples/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d seeded pixels of the 800x800 frame (%d evaluated samples, %.1f s)" % (n, ns, dt)}
+    threads = oracle.num_threads()
+    # one thread, on a sample sized for about 2 s
+    n1 = max(64, min(n, int(n * 2.0 / max(dt * threads, 1e-3))))
+    pix1 = synth.pixel_subset(800, 800, n1, seed=98)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, _, _, d1 = oracle.render_pixels(om, op, oc, pix1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    model_name = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model_name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded pixels of the 800x800 frame (%d evaluated samples, %.1f s)" % (n, ns, dt),
+            "single_thread_value": int(d1["n_eval"].sum()) / dt1,
+            "single_thread_sample": "%d seeded pixels, %.1f s" % (n1, dt1),
+            "host_cpu": model_name, "host_nproc": os.cpu_count()}
 
 
 def profile_run():
@@ -550,6 +610,7 @@ def main():
     mlp_ms, mlp_n = stages["mlp"]
     mlp_ms_per = mlp_ms / max(mlp_n, 1)
     achieved = MLP_FLOP_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e12
+    traffic = mlp_traffic()
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
     log("%.3f ms/frame, %.3g samples/s, mlp %.3f ms/launch" % (ms_step, value, mlp_ms_per))
 
@@ -583,9 +644,13 @@ def main():
         "order_ab": ab,
         "roofline": {"bound": "mfma", "kernel": "k_mlp_fwd_f32 (feature gather + MLP)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": mlp_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flop_per_launch": MLP_FLOP_PER_SAMPLE * samples_per_frame,
-                     "ms_per_launch": mlp_ms_per},
+                     "ms_per_launch": mlp_ms_per,
+                     "hbm_frac": (traffic / (mlp_ms_per * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None,
+                     "gather": {"requested_bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
+                                "effective_GBs": GATHER_BYTES_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e9,
+                                "l2_hit": MLP_L2_HIT if traffic else None}},
     }
     if not args.skip_hash:
         log("multi-level encoding workload")
@@ -605,6 +670,8 @@ def main():
     if not args.skip_fwd_bwd:
         log("fwd+bwd training step")
         out["fwd_bwd"] = fwd_bwd_bench(max(3, args.steps // 2))
+    log("on-box peak check (copy, FP32 GEMM)")
+    out["peaks_measured"] = measure_peaks()
     if not args.skip_cpu:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(scene)
