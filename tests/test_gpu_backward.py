@@ -90,6 +90,23 @@ def test_backward_multichunk_dense_bricks():
         assert r <= 1e-4, (k, r)
 
 
+def test_backward_non_cubic_grid():
+    """A 41 x 25 x 57 grid: bricks cut short differently on each axis, so the
+    owned vertex ranges and the tiles of the last bricks differ per axis."""
+    print_case("backward 41x25x57, 3000 rays, N=96")
+    dens, feats = synth.make_scene(64, seed=3)
+    dens = np.ascontiguousarray(dens[:41, :25, :57])
+    feats = np.ascontiguousarray(feats[:41, :25, :57])
+    p = Pair(0, dens=dens, feats=feats, mlp=synth.make_mlp(2, bias_std=0.1))
+    o, d = synth.random_rays(3000, seed=14)
+    gt = np.random.default_rng(4).uniform(0, 1, (3000, 3))
+    g, og = _run(p, 96, 0.0, o, d, gt, with_depth=True)
+    for k in NAMES:
+        r = _rel(to_np(g[k]), og[k])
+        print("%s rel %.2e" % (k, r))
+        assert r <= 1e-4, (k, r)
+
+
 def test_backward_full_size_training_step():
     """One MSE step: GT from the seed-10 scene rendered by the oracle, model
     grids N(0, 0.01) (seed 11), MLP seed 21, 8192 rays from 8 views,

@@ -113,3 +113,28 @@ def test_voxel_tiles_partitioned_launch(cus):
         a, b, c = (torch.nan_to_num(t, posinf=-1.0) for t in (a, b, c))
         assert torch.equal(a, b), name
         assert torch.equal(b, c), name
+
+
+def test_voxel_tiles_non_cubic_grid():
+    """A 41 x 25 x 57 grid (partial last bricks of different sizes on each
+    axis): the tiled BF16 path against ray order for both storage types."""
+    import paper_2404_11852_amd as cic
+    print_case("voxel tiles, 41x25x57 grid")
+    dens, feats = synth.make_scene(64, seed=3)
+    dens = np.ascontiguousarray(dens[:41, :25, :57])
+    feats = np.ascontiguousarray(feats[:41, :25, :57])
+    mlp = synth.make_mlp(2, bias_std=0.1)
+    rng = np.random.default_rng(5)
+    n = 20000
+    o = rng.normal(0.0, 0.4, (n, 3)) + np.array([0.2, -0.1, -3.0])
+    d = np.array([0.1, 0.05, 1.0]) + rng.normal(0.0, 0.2, (n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = torch.tensor(o, dtype=torch.float32, device="cuda")
+    d = torch.tensor(d, dtype=torch.float32, device="cuda")
+    for storage in (torch.float32, torch.float16):
+        m = cic.Model(dens, feats, mlp, device="cuda", storage=storage, density_shift=synth.DENSITY_SHIFT,
+                      compute=cic.CIC_BF16)
+        m.build_occupancy(synth.OCC_SIGMA)
+        ray, vox = _both_orders(m, 160, o, d)
+        _assert_equal(ray, vox)
+        assert vox[3] > 0
