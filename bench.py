@@ -78,8 +78,8 @@ def camera(W, H, pose):
 # passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
 # sources they were taken on (sha256 prefix of mlp.hip + mlp_common.h +
 # common.h + kernels.h).
-MLP_TRAFFIC_BYTES = 2.507e9 + 0.718e9
-MLP_TRAFFIC_SRC = "4c369ef47041c23f"
+MLP_TRAFFIC_BYTES = 2.516e9 + 0.717e9
+MLP_TRAFFIC_SRC = "cda35cb4de07139b"
 # L2 hit rate of the same launch (TCC_HIT / (TCC_HIT + TCC_MISS)), same passes
 MLP_L2_HIT = 0.854
 # feature bytes a sample's gather requests from the grid in the MLP kernel:

@@ -167,10 +167,8 @@ int generate_rays(const cic_camera *cam, int64_t n, const int64_t *pix,
  * opts->order = CIC_ORDER_VOXEL evaluates the MLP stage in voxel-bucket
  * order (the memory-centric ordering of Sec. IV-A; with BF16 compute on a
  * dense grid each brick's features are staged once in on-chip memory).
- * Opacity and depth equal ray order's bit for bit; colours do too with BF16
- * compute, and within float32 rounding with FP32 compute (ray order adds the
- * view-direction term of layer 0 from a per-ray table, voxel order per
- * sample).
+ * Results equal ray order's bit for bit (each sample's colour depends only
+ * on its own inputs, and the compositing reads samples in ray order).
  * rgb [n][3], depth_t [n], acc [n]: device float32.  n_eval (device int64,
  * nullable) is increased by the number of samples that went through the MLP. */
 int render_rays(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,

@@ -198,7 +198,7 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
     b.rec_k = cv.take<uint16_t>(ns);
     b.rec_w = cv.take<float>(ns);
     b.rec_c = cv.take<float>(3 * ns);
-    if (!voxel) b.z0 = cv.take<float>(128 * nc);
+    b.z0 = cv.take<float>(128 * nc);
     b.enc = cv.take<uint32_t>(16 * nc);
     if (voxel) {
         b.rec_key = cv.take<uint32_t>(ns);
@@ -440,7 +440,7 @@ void run_pipeline(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, con
             launch_brick_scatter(b, s);
         }
     }
-    if (!voxel && mlp->compute == CIC_F32) {
+    if (mlp->compute == CIC_F32) {
         StageTimer t(CIC_STAGE_EMBED, s);
         launch_ray_embed(*mlp, b, s);
     }

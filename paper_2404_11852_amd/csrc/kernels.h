@@ -35,7 +35,7 @@ struct RenderBufs {
     float *stage;          // [n*N][kStageStride] per-sample MLP vectors (adjoint only; nullable)
     uint32_t *stage_mask;  // [n*N][8] ReLU masks of the staged h1 (words 0-3) and h2 (words 4-7): word q, bit
                            // 4t + r is row 16t + 4q + r > 0 (adjoint only)
-    float *z0;             // [n][128] per-ray direction term of layer 0 (ray order)
+    float *z0;             // [n][128] per-ray direction term of layer 0 (FP32 compute)
     uint32_t *enc;         // [n][16] per-ray view encoding in BF16: lane group q's 7 inputs in words 4q..4q+3
     // voxel order
     uint32_t *rec_key;     // [n*N] brick of each live sample

@@ -352,10 +352,12 @@ static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bo
                        voxel ? 1 : 0);
 }
 
-// FP32 in ray order uses the per-ray direction table (b.z0 must be filled
-// by launch_ray_embed first); voxel order and the BF16 kernel evaluate the
-// encoding per sample (measured: in the vector-ALU-bound BF16 kernel the
-// table's extra loads cost more than the per-sample encoding they replace).
+// FP32, in either order, uses the per-ray direction table (b.z0 must be
+// filled by launch_ray_embed first): in voxel order the samples of a ray
+// within a brick are consecutive, so the table rows stay cached (measured
+// on eight 800x800 views: MLP 145.1 -> 128.3 ms, against 125.8 ms in ray
+// order), and both orders then give the same bits.  The BF16 kernel reads a
+// per-ray BF16 encoding table instead.
 template <typename T>
 void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
@@ -363,8 +365,7 @@ void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, b
         launch_mlp_forward_bf16<T>(g, m, b, voxel, s);
         return;
     }
-    if (voxel) launch_fwd<T, false, false>(g, m, b, true, s);
-    else launch_fwd<T, false, true>(g, m, b, false, s);
+    launch_fwd<T, false, true>(g, m, b, voxel, s);
 }
 
 void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
