@@ -302,6 +302,9 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
     // one batch of kBfNT tiles: samples s0 + nt*16 + j below send (TILE:
     // positions in the staged segment)
     auto batch = [&](int64_t s0, int64_t send) {
+        // wave priority raised at each layer, as in the FP32 kernel (measured:
+        // MLP stage 27.0 -> 26.7 ms in voxel order, 45.3 -> 45.0 ms in ray order)
+        __builtin_amdgcn_s_setprio(0);
         bf8_t xin[kBfNT][2];
         int64_t rec[kBfNT];
         bool valid[kBfNT];
@@ -343,6 +346,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
 
         }
         // layer 0
+        __builtin_amdgcn_s_setprio(1);
         f4_t h1[8][kBfNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
 #pragma unroll
             for (int nt = 0; nt < kBfNT; ++nt) hb[c][nt] = relu_bf8(pack_bf8(h1[2 * c][nt], h1[2 * c + 1][nt]));
         // layer 1
+        __builtin_amdgcn_s_setprio(2);
         f4_t h2[8][kBfNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -386,6 +391,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
             __builtin_amdgcn_sched_barrier(0);
         }
         // layer 2 (one zero-padded tile)
+        __builtin_amdgcn_s_setprio(3);
         f4_t o3[kBfNT];
 #pragma unroll
         for (int nt = 0; nt < kBfNT; ++nt) o3[nt] = *(const f4_t *)(fl + kBfB2);
