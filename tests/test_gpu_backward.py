@@ -146,3 +146,27 @@ def test_autograd_function_matches_direct_call():
     for leaf, k in zip(leaves, NAMES):
         ref = g[k]
         assert torch.allclose(leaf.grad, ref, rtol=1e-5, atol=1e-7 * float(ref.abs().max()) + 1e-12), k
+
+
+def test_backward_degenerate_inputs():
+    """No rays, and rays that all miss the grid (no live samples, so no brick
+    segments): the accumulated gradients stay exactly zero; a zero upstream
+    gradient on rays that hit gives zero gradients too."""
+    import paper_2404_11852_amd as cic
+    print_case("backward degenerate inputs")
+    p = Pair(24, seed=4, mlp_seed=5, bias_std=0.1)
+    go = cic.make_opts(64)
+    z = torch.empty((0, 3), device="cuda")
+    g = cic.render_backward(p.gpu, go, z, z, z)
+    torch.cuda.synchronize()
+    assert all(float(v.abs().max()) == 0.0 for v in g.values() if v.numel())
+    o = torch.tensor([[5.0, 5.0, 5.0]] * 40, device="cuda")
+    d = torch.tensor([[1.0, 0.0, 0.0]] * 40, device="cuda")
+    g = cic.render_backward(p.gpu, go, o, d, torch.ones((40, 3), device="cuda"))
+    torch.cuda.synchronize()
+    assert all(float(v.abs().max()) == 0.0 for v in g.values())
+    o2, d2 = synth.random_rays(100, seed=3)
+    g = cic.render_backward(p.gpu, go, torch.from_numpy(o2).cuda(), torch.from_numpy(d2).cuda(),
+                            torch.zeros((100, 3), device="cuda"))
+    torch.cuda.synchronize()
+    assert all(float(v.abs().max()) == 0.0 for v in g.values())
