@@ -252,12 +252,11 @@ SeqBufs carve_seq(Carver &cv, int64_t np, const cic_opts *o, int64_t nb)
 }
 
 // Adjoint passes of up to 8192 rays.  The samples are processed in brick
-// order (the voxel-order bucketing of the forward) so that the feature
-// gradients can be accumulated per brick in LDS and added to the grid once
-// per brick (measured on the 8192-ray training step: 12.05 -> 7.6 ms against
-// per-sample global atomics in ray order).
+// order (the voxel-order bucketing of the forward) so that the grid
+// gradients can be accumulated per brick segment on chip and added to the
+// grid once per vertex (measured on the 8192-ray training step: 12.05 ms
+// with per-sample global atomics in ray order).
 constexpr int64_t kChunkRaysBwd = 8192;
-constexpr bool kBwdVoxel = true;
 
 // Extra buffers of a backward pass (after carve_render's).
 void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &bb)
@@ -269,9 +268,9 @@ void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &
     b.stage_mask = cv.take<uint32_t>(ns * 8);
     bb.rec_dc = cv.take<float>(3 * ns);
     bb.partials = cv.take<float>((int64_t)kWgBlocks * kPartialFloats);
-    bb.df_sorted = kBwdVoxel ? cv.take<float>(12 * ns) : nullptr;
-    bb.rec_draw = kBwdVoxel ? cv.take<float>(ns) : nullptr;
-    bb.seg_tiles = kBwdVoxel ? cv.take<float>(fg_max_segments(b.n_bricks, ns) * kFgTileFloats) : nullptr;
+    bb.df_sorted = cv.take<float>(12 * ns);
+    bb.rec_draw = cv.take<float>(ns);
+    bb.seg_tiles = cv.take<float>(fg_max_segments(b.n_bricks, ns) * kFgTileFloats);
 }
 
 size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
@@ -307,7 +306,7 @@ size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
     }
     case CIC_OP_RENDER_BACKWARD: {
         const int64_t nc = n < kChunkRaysBwd ? n : kChunkRaysBwd;
-        RenderBufs b = carve_render(cv, nc, o->n_samples, nb, kBwdVoxel, false);
+        RenderBufs b = carve_render(cv, nc, o->n_samples, nb, true, false);
         BackwardBufs bb{};
         carve_backward(cv, nc, o->n_samples, b, bb);
         break;
@@ -990,7 +989,7 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     for (int64_t c0 = 0; c0 < n_rays; c0 += kChunkRaysBwd) {
         const int64_t nc = (n_rays - c0) < kChunkRaysBwd ? (n_rays - c0) : kChunkRaysBwd;
         Carver cv(align_ws(ws));
-        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, kBwdVoxel, false);
+        RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, true, false);
         BackwardBufs bb{};
         carve_backward(cv, nc, opts->n_samples, b, bb);
         b.rays_o = rays_o + 3 * c0;
@@ -1013,16 +1012,16 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         {
             StageTimer t(CIC_STAGE_COMPACT, s);
             launch_exclusive_scan(b.count, b.offsets, b.scan_tmp, b.n, s);
-            if (kBwdVoxel) launch_fill_u32(b.brick_off, 0u, b.n_bricks + 1, s);
-            launch_compact(gk, b, kBwdVoxel, s);
-            if (kBwdVoxel) {
+            launch_fill_u32(b.brick_off, 0u, b.n_bricks + 1, s);
+            launch_compact(gk, b, true, s);
+            {
                 launch_exclusive_scan(b.brick_off, b.brick_off, b.brick_tmp, b.n_bricks, s);
                 launch_brick_scatter(b, s);
             }
         }
         {
             StageTimer t(CIC_STAGE_MLP, s);
-            launch_mlp_forward_staged(gk, *mlp, b, kBwdVoxel, s);
+            launch_mlp_forward_staged(gk, *mlp, b, true, s);
         }
         {
             StageTimer t(CIC_STAGE_BACKWARD, s);
@@ -1030,8 +1029,8 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         }
         {
             StageTimer t(CIC_STAGE_BWD_MLP, s);
-            launch_mlp_backward(gk, *mlp, b, bb, kBwdVoxel, s);
-            if (kBwdVoxel) launch_feature_grads_bricks(gk, b, bb, s);
+            launch_mlp_backward(gk, *mlp, b, bb, s);
+            launch_feature_grads_bricks(gk, b, bb, s);
         }
         {
             StageTimer t(CIC_STAGE_BWD_WGRAD, s);

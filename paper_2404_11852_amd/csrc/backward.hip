@@ -8,15 +8,19 @@
 // expected distance gives delta (T_{k+1} t_k - D_k) with D_k = sum_{j>k} w_j t_j,
 // and the opacity 1 - T_stop gives delta T_stop.  dC/dc_k = w_k.
 //
-// Kernels (one backward pass over a chunk of rays; the forward has already
-// been recomputed into the workspace, with per-sample MLP vectors staged):
+// Kernels (one backward pass over a chunk of rays, samples in brick order;
+// the forward has already been recomputed into the workspace, with
+// per-sample MLP vectors and ReLU sign masks staged):
 //  - k_bwd_composite: one wavefront per ray walks its live samples from the
 //    back, 64 at a time, with a reverse wavefront scan for R_k and D_k; it
-//    writes dL/dc_k and scatter-adds dL/draw through the trilinear weights.
+//    writes dL/dc_k and dL/draw per sample.
 //  - k_mlp_bwd: per 32-sample batch, the output-layer adjoint on the vector
 //    ALUs, then W1^T and W0^T products on FP32 MFMA (transposed weight
 //    fragments in LDS); hidden-layer gradients are staged for the weight
-//    gradients and the feature gradient is scatter-added to the grid.
+//    gradients and the 12 feature gradients written in brick order.
+//  - k_fgrad_seg, k_fgrad_gather: the feature and raw-density gradients of
+//    each brick segment summed per tile vertex on chip, then added to the
+//    grids per vertex in a fixed order (no atomics).
 //  - k_wgrad: weight gradients as split-K MFMA products over the staged
 //    per-sample vectors, one partial per block, reduced in a fixed order by
 //    k_wgrad_apply (deterministic).
@@ -36,18 +40,6 @@ __device__ __forceinline__ float wave_rev_incl_scan(float v)
         if (l + off < kWave) v += u;
     }
     return v;
-}
-
-__device__ __forceinline__ void scatter_trilinear(float *grad, const GridK &g, const int i0[3], const float fr[3],
-                                                  int stride, int ch, float v)
-{
-    const float wx[2] = {1.f - fr[0], fr[0]}, wy[2] = {1.f - fr[1], fr[1]}, wz[2] = {1.f - fr[2], fr[2]};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-        const float w = wx[dx] * wy[dy] * wz[dz];
-        atomicAdd(grad + vertex_index(g, i0[0] + dx, i0[1] + dy, i0[2] + dz) * stride + ch, w * v);
-    }
 }
 
 __global__ __launch_bounds__(256) void k_bwd_composite(GridK g, OptsK op, RenderBufs b, BackwardBufs bb)
@@ -106,8 +98,7 @@ __global__ __launch_bounds__(256) void k_bwd_composite(GridK g, OptsK op, Render
             ds *= inf.delta;
             const float raw = trilerp1(dens, g, i0, fr, 1, 0);
             const float draw = ds * sigmoidf(raw + g.shift);
-            if (bb.rec_draw) bb.rec_draw[r] = draw;   // added per brick with the feature gradients
-            else scatter_trilinear(bb.d_density, g, i0, fr, 1, 0, draw);
+            bb.rec_draw[r] = draw;   // added per brick segment with the feature gradients
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) bb.rec_dc[3 * r + ch] = w * gr[ch];
         }
@@ -136,8 +127,7 @@ constexpr int kBOffW0T = kBOffW1T + 8 * 8 * 64 * 4;
 constexpr int kBOffW2 = kBOffW0T + 8 * 64 * 4;
 constexpr int kBLds = kBOffW2 + 384;
 
-__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb,
-                                                               int voxel)
+__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
 {
     extern __shared__ float lds[];
     const int nthr = blockDim.x;
@@ -163,7 +153,6 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
     const f4_t *w1t = (const f4_t *)(lds + kBOffW1T);
     const f4_t *w0t = (const f4_t *)(lds + kBOffW0T);
     const f4_t *w2l = (const f4_t *)(lds + kBOffW2);
-    float *dfeat_grad = bb.d_features;
 
     const BatchRange br = xcd_batches(nbatch, kBwdWaves, wave);
     for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
@@ -175,7 +164,7 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
         for (int nt = 0; nt < kBNT; ++nt) {
             const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
             valid[nt] = s < total;
-            rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
+            rec[nt] = valid[nt] ? (int64_t)b.perm[s] : 0;
             const uint32_t h2m = valid[nt] ? b.stage_mask[rec[nt] * 8 + 4 + q] : 0u;
             h1m[nt] = valid[nt] ? b.stage_mask[rec[nt] * 8 + q] : 0u;
             float dl[3] = {0.f, 0.f, 0.f};
@@ -253,32 +242,12 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
                 for (int nt = 0; nt < kBNT; ++nt)
                     df[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp0[c4][nt][rr], df[nt], 0, 0, 0);
         }
-        if (bb.df_sorted) {
-            // brick-tile mode: keep the 12 feature gradients of the sample at its
-            // position in brick order; k_fgrad_brick accumulates them
-#pragma unroll
-            for (int nt = 0; nt < kBNT; ++nt) {
-                const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
-                if (valid[nt] && q < 3) *(f4_t *)(bb.df_sorted + s * 12 + 4 * q) = df[nt];
-            }
-            continue;
-        }
+        // the 12 feature gradients of the sample at its position in brick order;
+        // the brick-segment kernel accumulates them
 #pragma unroll
         for (int nt = 0; nt < kBNT; ++nt) {
-            if (!valid[nt] || q >= 3) continue;
-            const uint32_t ray = b.rec_ray[rec[nt]];
-            const RayInfo inf = b.info[ray];
-            float o[3], d[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                o[a] = b.rays_o[3 * (int64_t)ray + a];
-                d[a] = b.rays_d[3 * (int64_t)ray + a];
-            }
-            int i0[3];
-            float fr[3], tk;
-            sample_voxel(o, d, inf.tn, inf.delta, b.rec_k[rec[nt]], g, i0, fr, tk);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) scatter_trilinear(dfeat_grad, g, i0, fr, 12, 4 * q + r, df[nt][r]);
+            const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
+            if (valid[nt] && q < 3) *(f4_t *)(bb.df_sorted + s * 12 + 4 * q) = df[nt];
         }
     }
 }
@@ -486,8 +455,7 @@ void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const Back
     hipLaunchKernelGGL(k_fgrad_gather, dim3((unsigned)b.n_bricks), dim3(256), 0, s, g, nb0, b, bb);
 }
 
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
-                         hipStream_t s)
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
     const int lds = kBLds * (int)sizeof(float);
     static bool attr_set = false;
@@ -495,7 +463,7 @@ void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, 
         (void)hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb, voxel ? 1 : 0);
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb);
 }
 
 // ---------------------------------------------------------------------------

@@ -115,9 +115,9 @@ struct BackwardBufs {
     float *d_w0, *d_b0, *d_w1, *d_b1, *d_w2, *d_b2;
     float *rec_dc;         // [n*N*3] dL/dc per live sample
     float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
-    float *df_sorted;      // [n*N][12] feature gradient per sample in brick order (brick-tile mode), else null
-    float *rec_draw;       // [n*N] raw-density gradient per live sample (brick-tile mode), else null
-    float *seg_tiles;      // [max segments][kFgTileFloats] each segment's accumulated gradient tile (brick-tile mode)
+    float *df_sorted;      // [n*N][12] feature gradient per sample in brick order
+    float *rec_draw;       // [n*N] raw-density gradient per live sample
+    float *seg_tiles;      // [max segments][kFgTileFloats] each segment's accumulated gradient tile
 };
 // 9^3 vertices x (12 feature + 1 density) gradient channels per brick tile
 constexpr int kFgTileFloats = (kBrick + 1) * (kBrick + 1) * (kBrick + 1) * 13;
@@ -127,8 +127,7 @@ constexpr int kWgBlocks = 1024;
 constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 * 16;
 void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
                                hipStream_t s);
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, bool voxel,
-                         hipStream_t s);
+void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
 void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
 // brick-tile accumulation of the feature and density gradients written by the
 // MLP backward and the compositing adjoint, then their addition to the grids
