@@ -282,6 +282,14 @@ __device__ __forceinline__ bf8_t relu_bf8(bf8_t v)
     return __builtin_bit_cast(bf8_t, s);
 }
 
+// Output sigmoid of the BF16 path from the hardware base-2 exponential and
+// reciprocal (about 1e-7 relative error, far inside the path's BF16 input
+// rounding): 1 / (1 + 2^(-x log2 e)).
+__device__ __forceinline__ float sigmoid_hw(float x)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * x));
+}
+
 // TILE: voxel order with the brick's features staged in LDS (dense grids).
 template <typename T, bool TILE>
 __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
@@ -347,21 +355,18 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         }
         // layer 0
         __builtin_amdgcn_s_setprio(1);
+        // (each tile's first MFMA takes the bias as its accumulator input)
         f4_t h1[8][kBfNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const f4_t bias = *(const f4_t *)(fl + kBfB0 + 16 * t + 4 * q);
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt) h1[t][nt] = bias;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-#pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < kBfNT; ++nt)
-                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], h1[t][nt], 0, 0, 0);
+                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], c == 0 ? bias : h1[t][nt], 0, 0,
+                                                                        0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -377,40 +382,35 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         for (int t = 0; t < 8; ++t) {
             const f4_t bias = *(const f4_t *)(fl + kBfB1 + 16 * t + 4 * q);
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt) h2[t][nt] = bias;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const bf8_t a = frag[kBfW1 + (t * 4 + c) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < kBfNT; ++nt)
-                    h2[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][nt], h2[t][nt], 0, 0, 0);
+                    h2[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][nt], c == 0 ? bias : h2[t][nt], 0, 0,
+                                                                        0);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
         // layer 2 (one zero-padded tile)
         __builtin_amdgcn_s_setprio(3);
         f4_t o3[kBfNT];
-#pragma unroll
-        for (int nt = 0; nt < kBfNT; ++nt) o3[nt] = *(const f4_t *)(fl + kBfB2);
+        const f4_t bias2 = *(const f4_t *)(fl + kBfB2);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const bf8_t a = frag[kBfW2 + c * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < kBfNT; ++nt)
                 o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, relu_bf8(pack_bf8(h2[2 * c][nt], h2[2 * c + 1][nt])),
-                                                                 o3[nt], 0, 0, 0);
+                                                                 c == 0 ? bias2 : o3[nt], 0, 0, 0);
         }
         // lanes of group 0 hold rows 0..3 (colour channels 0..2) of their sample
 #pragma unroll
         for (int nt = 0; nt < kBfNT; ++nt) {
             if (valid[nt] && q == 0) {
                 float *out = b.rec_c + 3 * rec[nt];
-                out[0] = sigmoidf(o3[nt][0]);
-                out[1] = sigmoidf(o3[nt][1]);
-                out[2] = sigmoidf(o3[nt][2]);
+                out[0] = sigmoid_hw(o3[nt][0]);
+                out[1] = sigmoid_hw(o3[nt][1]);
+                out[2] = sigmoid_hw(o3[nt][2]);
             }
         }
     };
