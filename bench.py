@@ -99,6 +99,36 @@ def mlp_traffic():
     return MLP_TRAFFIC_BYTES if h.hexdigest()[:16] == MLP_TRAFFIC_SRC else None
 
 
+def stage_rooflines(stage_ms, live, rays):
+    """Fractions of the frame's other stages against their bounds, from
+    lower-bound algorithmic work on counts the host knows (live samples and
+    rays of the frame): the march writes each live sample's slot (index 2 B,
+    weight 4 B) and per ray its interval record and count (20 B) after reading
+    the ray (24 B) -- its occupancy and density reads depend on the scene and
+    are left out, so its figure is a floor; the compaction reads the slots
+    (6 B) and writes the ray-ordered records (ray 4, index 2, weight 4 B),
+    plus the ray's count and offset (8 B); the reduce reads weight and colour
+    (16 B) per live sample and writes colour, depth and opacity (20 B) per
+    ray; the per-ray direction term costs 6,912 FLOP per ray on the vector
+    ALUs (FP32 vector peak 157.3 TFLOP/s)."""
+    out = {}
+    work = {"march": (6 * live + 44 * rays, "hbm"), "compact": (16 * live + 8 * rays, "hbm"),
+            "reduce": (16 * live + 20 * rays, "hbm"), "embed": (6912 * rays, "valu")}
+    for k, (w, bound) in work.items():
+        ms = stage_ms.get(k, 0.0)
+        if ms <= 0:
+            continue
+        if bound == "hbm":
+            gbs = w / (ms * 1e-3) / 1e9
+            out[k] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": gbs / PEAK_HBM_GBS, "bytes": w}
+        else:
+            tf = w / (ms * 1e-3) / 1e12
+            out[k] = {"bound": "valu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                      "frac": tf / PEAK_FP32_TFLOPS, "flop": w}
+    return out
+
+
 def measure_peaks():
     """On-box check of the published peaks the fractions use: a 2 GiB
     device-to-device copy (read + write bytes per second) and an 8192^3
@@ -641,6 +671,7 @@ def main():
         "fps_full_800x800": 1e3 / ms_step,
         "evaluated_samples_per_frame": samples_per_frame,
         "stage_ms_per_launch": stage_ms,
+        "stage_rooflines": stage_rooflines(stage_ms, samples_per_frame, W * H),
         "order_ab": ab,
         "roofline": {"bound": "mfma", "kernel": "k_mlp_fwd_f32 (feature gather + MLP)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
