@@ -479,7 +479,11 @@ void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, 
 // partials in block order (deterministic).
 // ---------------------------------------------------------------------------
 constexpr int kWgStep = 16;
-constexpr int kWgRow = kStageStride + 4;   // padded LDS row
+// Padded LDS row: an MFMA operand read takes 16 consecutive columns of 4
+// consecutive rows, so a row stride of 16 (mod 64) words puts the 64 lanes on
+// 64 distinct banks.
+constexpr int kWgRow = kStageStride + 24;
+static_assert(kWgRow % 64 == 16, "wgrad LDS row stride");
 constexpr int kWgTiles = 24 + 64 + 8 + 8 + 1;
 constexpr int kWgWaves = 8;
 constexpr int kWgTPW = (kWgTiles + kWgWaves - 1) / kWgWaves;
