@@ -614,8 +614,8 @@ def main():
                     help="run the short fixed workload used for rocprofv3 counter passes and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rays would shard by pixel tiles with the grid replicated; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rays would shard by pixel tiles with the grid replicated). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -30,7 +30,7 @@
  * path takes those decisions in float32.  The float32 fraction inside the
  * voxel is promoted to float64 before the trilinear weights are formed.
  *
- * Readings of points the paper leaves open are listed in the design notes:
+ * Readings taken where the paper leaves a point open:
  * softplus density with an additive shift applied after interpolation,
  * per-ray step delta = (t_far - t_near)/N at interval midpoints,
  * align-corners vertex placement, early termination when transmittance

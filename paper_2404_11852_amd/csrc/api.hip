@@ -528,7 +528,7 @@ int side_sync(SideSync **out)
 }
 
 // CU-partitioned stream pair for render_sequence: per XCD, `t` CUs for the
-// targets and the rest for the references.  The driver spreads the bits of a
+// targets and the rest for the references.  The HIP runtime spreads the bits of a
 // stream's CU mask over the chip interleaved: bit i goes to XCD i % 8, and
 // within the XCD bit i / 8 goes to shader engine (i / 8) % 4.  The targets
 // take bits [0, 8t) and the references the rest, so every XCD gets t target
