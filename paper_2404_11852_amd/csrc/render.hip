@@ -365,33 +365,44 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
 // wavefront per ray: lanes read consecutive live samples (coalesced) and a
 // butterfly sum combines them in a fixed order, so the result does not
 // depend on the order in which the MLP stage produced the colours.
+// Per-ray accumulation, four rays per wavefront (16 lanes each): lane l of a
+// ray's group sums w_k c_k over its live samples l, l + 16, l + 32, ... in
+// order, then a 16-lane butterfly adds the lanes' partial sums (a fixed
+// order, so the result is deterministic and the same in every sample order
+// of the MLP stage).  The four rays' loads go out together, which is what a
+// stage bound by the latency of its dependent loads needs.
+constexpr int kReduceLanes = 16;
+constexpr int kReduceRays = kRayWaves * (kWave / kReduceLanes);   // rays per 256-thread block
+
+__device__ __forceinline__ float group16_sum(float v)
+{
+#pragma unroll
+    for (int off = kReduceLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kReduceLanes);
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(RenderBufs b, OptsK op, float *rgb, float *depth, float *acc,
                                                 const int32_t *out_map, cic_camera cam, int frame,
                                                 unsigned long long *n_eval)
 {
-    const int lane = lane_id();
-    const int64_t ray = (int64_t)blockIdx.x * kRayWaves + (threadIdx.x / kWave);
-    if (n_eval && ray == 0 && lane == 0) atomicAdd(n_eval, (unsigned long long)b.offsets[b.n]);
-    if (ray >= b.n) return;
+    const int sub = (int)(threadIdx.x % kReduceLanes);
+    const int64_t ray = (int64_t)blockIdx.x * kReduceRays + (threadIdx.x / kReduceLanes);
+    if (n_eval && ray == 0 && sub == 0) atomicAdd(n_eval, (unsigned long long)b.offsets[b.n]);
     const uint32_t n_act = b.n_active ? *b.n_active : (uint32_t)b.n;
-    if ((uint64_t)ray >= n_act) return;
-    const uint32_t cnt = b.count[ray], off = b.offsets[ray];
+    const bool active = ray < b.n && (uint64_t)ray < n_act;
+    const uint32_t cnt = active ? b.count[ray] : 0u, off = active ? b.offsets[ray] : 0u;
     float r = 0.f, gg = 0.f, bb = 0.f;
-    for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
-        const uint32_t j = j0 + lane;
-        float pr = 0.f, pg = 0.f, pb = 0.f;
-        if (j < cnt) {
-            const int64_t k = (int64_t)off + j;
-            const float w = b.rec_w[k];
-            pr = w * b.rec_c[3 * k];
-            pg = w * b.rec_c[3 * k + 1];
-            pb = w * b.rec_c[3 * k + 2];
-        }
-        r += wave_sum(pr);
-        gg += wave_sum(pg);
-        bb += wave_sum(pb);
+    for (uint32_t j = (uint32_t)sub; j < cnt; j += kReduceLanes) {
+        const int64_t k = (int64_t)off + j;
+        const float w = b.rec_w[k];
+        r = fmaf(w, b.rec_c[3 * k], r);
+        gg = fmaf(w, b.rec_c[3 * k + 1], gg);
+        bb = fmaf(w, b.rec_c[3 * k + 2], bb);
     }
-    if (lane != 0) return;
+    r = group16_sum(r);
+    gg = group16_sum(gg);
+    bb = group16_sum(bb);
+    if (!active || sub != 0) return;
     const RayInfo inf = b.info[ray];
     const float ts = inf.t_stop;
     const int64_t out = out_map ? (int64_t)out_map[ray] : ray;
@@ -416,7 +427,7 @@ __global__ __launch_bounds__(256) void k_reduce(RenderBufs b, OptsK op, float *r
 void launch_reduce(const RenderBufs &b, const OptsK &o, float *rgb, float *depth, float *acc,
                    const int32_t *out_map, const cic_camera *frame_cam, int64_t *n_eval, hipStream_t s)
 {
-    const int64_t blocks = (b.n + kRayWaves - 1) / kRayWaves;
+    const int64_t blocks = (b.n + kReduceRays - 1) / kReduceRays;
     cic_camera cam{};
     if (frame_cam) cam = *frame_cam;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, b, o, rgb, depth, acc,
