@@ -257,6 +257,8 @@ def sparw_orbit(model, opts, W, H, n_frames=32, ref_every=16, max_angle_deg=0.0,
         "mask_fraction_mean": sum(fr) / len(fr), "mask_fraction_max": max(fr),
         "psnr_vs_full_mean_db": sum(ps) / len(ps), "psnr_vs_full_min_db": min(ps),
     }
+    # per-target stage times (warp, then the hole rays through march ... reduce)
+    res["stage_ms_per_target"] = {k: v[0] / n_t for k, v in st.items() if v[1]}
     warp_ms, warp_n = st["warp"]
     if warp_n:
         gbs = WARP_BYTES_PER_PIXEL * W * H / (warp_ms / warp_n * 1e-3) / 1e9
