@@ -302,7 +302,10 @@ int render_frame_ds(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
  * d_depth_t [n] (nullable), d_acc [n] (nullable).  Accumulates (+=) into
  * d_density [res0][res1][res2], d_features [res0][res1][res2][12] and the
  * MLP gradients shaped like the weights (all float32, device).  float32
- * grids and CIC_F32 compute only. */
+ * grids and CIC_F32 compute only.  The MLP gradients are the same bits on
+ * every call; the grid gradients can differ in their last bits between
+ * calls, because the samples of a brick are summed in the order the
+ * bucketing's atomic cursors placed them. */
 int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, int64_t n_rays,
                     const float *rays_o, const float *rays_d,
                     const float *d_rgb, const float *d_depth_t, const float *d_acc,

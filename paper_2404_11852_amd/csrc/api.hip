@@ -1034,7 +1034,7 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         }
         {
             StageTimer t(CIC_STAGE_BWD_WGRAD, s);
-            launch_weight_grads(b, bb, s);
+            launch_weight_grads(*mlp, b, bb, s);
         }
     }
     return after_launch("render_backward");

@@ -184,10 +184,9 @@ __global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp 
                     dp1[t][nt][r] = ((h2m >> (4 * t + r)) & 1u) ? v : 0.f;
                 }
             }
+            // dp1 itself is recomputed by the weight-gradient kernel
             if (valid[nt]) {
                 float *wrow = b.stage + rec[nt] * kStageStride;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) *(f4_t *)(wrow + kStDP1 + 16 * t + 4 * q) = dp1[t][nt];
                 *(f4_t *)(wrow + kStDL + 4 * q) = (q == 0) ? f4_t{dl[0], dl[1], dl[2], 0.f} : f4_t{0.f, 0.f, 0.f, 0.f};
             }
         }
@@ -474,15 +473,15 @@ void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, 
 //   P3 = dp1^T [x|1][32:48]    (128 x 16: db1 in column 7)
 //   P4 = dl^T [x|1][32:48]     (16 x 16: db2 in column 7)
 // one fused pass: each block owns a contiguous range of samples, stages 16
-// full rows at a time in LDS and runs all 105 output tiles on FP32 MFMA
+// stored rows at a time in LDS, recomputes their dp1 there and runs all 105 output tiles on FP32 MFMA
 // (K = samples), writing one partial per block; k_wgrad_apply adds the
 // partials in block order (deterministic).
 // ---------------------------------------------------------------------------
 constexpr int kWgStep = 16;
-// Padded LDS row: an MFMA operand read takes 16 consecutive columns of 4
-// consecutive rows, so a row stride of 16 (mod 64) words puts the 64 lanes on
-// 64 distinct banks.
-constexpr int kWgRow = kStageStride + 24;
+// Padded LDS row (the stored row, then the recomputed dp1): an MFMA operand
+// read takes 16 consecutive columns of 4 consecutive rows, so a row stride of
+// 16 (mod 64) words puts the 64 lanes on 64 distinct banks.
+constexpr int kWgRow = kStDP1 + 128 + 24;
 static_assert(kWgRow % 64 == 16, "wgrad LDS row stride");
 constexpr int kWgTiles = 24 + 64 + 8 + 8 + 1;
 constexpr int kWgWaves = 8;
@@ -513,7 +512,7 @@ __device__ __forceinline__ WgTile wg_tile(int t)
 }
 
 __global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, const uint32_t *total_p, float *partials,
-                                               int64_t slab)
+                                               int64_t slab, const float *w2)
 {
     __shared__ float rows[kWgStep * kWgRow];
     const int lane = lane_id(), wave = threadIdx.x / 64;
@@ -527,6 +526,13 @@ __global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, 
     // The rows of the next step are loaded into registers while this step's
     // MFMAs run, then written to LDS (one step of software pipelining).
     constexpr int kThreads = kWgWaves * 64;
+    static_assert(kThreads % 128 == 0, "dp1 fill: whole rows per pass");
+    // dp1 fill: thread t owns hidden unit t % 128 of rows t / 128, t / 128 +
+    // kThreads / 128, ...; the MLP backward's expression and mask, so the
+    // same bits (computing it while storing the rows, from a second load of
+    // the logit gradient, measured slower: 1.58 against 1.41 ms per step)
+    const int hu = threadIdx.x % 128;
+    const float w2a = w2[hu], w2b = w2[128 + hu], w2c = w2[256 + hu];
     constexpr int kPer = (kWgStep * kF4Row + kThreads - 1) / kThreads;
     f4_t pre[kPer];
     auto load_step = [&](int64_t sb) {
@@ -544,6 +550,12 @@ __global__ __launch_bounds__(kWgWaves * 64, 2) void k_wgrad(const float *stage, 
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + i * kThreads;
             if (e < kWgStep * kF4Row) *(f4_t *)(rows + (e / kF4Row) * kWgRow + 4 * (e % kF4Row)) = pre[i];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x / 128; r < kWgStep; r += kThreads / 128) {
+            float *row = rows + r * kWgRow;
+            const float v = fmaf(w2a, row[kStDL], fmaf(w2b, row[kStDL + 1], w2c * row[kStDL + 2]));
+            row[kStDP1 + hu] = row[kStH2 + hu] > 0.f ? v : 0.f;
         }
         __syncthreads();
         if (sb + kWgStep < s1) load_step(sb + kWgStep);
@@ -637,13 +649,13 @@ __global__ __launch_bounds__(kApplyOut * kApplyGroups) void k_wgrad_apply(const 
     }
 }
 
-void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
+void launch_weight_grads(const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
     // sample range per block from the pass's maximum sample count
     const int64_t max_s = b.n * (int64_t)b.n_samples;
     const int64_t slab = ((max_s + kWgBlocks - 1) / kWgBlocks + kWgStep - 1) / kWgStep * kWgStep;
     hipLaunchKernelGGL(k_wgrad, dim3(kWgBlocks), dim3(kWgWaves * 64), 0, s, (const float *)b.stage, b.offsets + b.n,
-                       bb.partials, slab);
+                       bb.partials, slab, m.w2);
     const int n_out = 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3;
     hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + kApplyOut - 1) / kApplyOut), dim3(kApplyOut * kApplyGroups), 0, s,
                        (const float *)bb.partials, kWgBlocks, bb);

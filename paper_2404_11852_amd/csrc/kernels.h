@@ -51,10 +51,14 @@ struct RenderBufs {
 
 // Per-sample row of MLP vectors kept for the weight gradients (adjoint):
 // inputs with a constant 1 in the padding slot (so the bias gradient falls
-// out of the same product), both hidden activations, both hidden-layer
-// pre-activation gradients and the output-logit gradient.
-constexpr int kStX = 0, kStH1 = 40, kStH2 = 168, kStDP0 = 296, kStDP1 = 424, kStDL = 552;
-constexpr int kStageStride = 568;   // the logit-gradient block is 16 wide (3 used, rest zero)
+// out of the same product), both hidden activations, the first hidden
+// layer's pre-activation gradient and the output-logit gradient.  The second
+// layer's pre-activation gradient, dp1 = [h2 > 0] (W2^T dlogit), is not
+// stored: the weight-gradient kernel recomputes it from the row into its LDS
+// copy, at kStDP1 just past the stored part.
+constexpr int kStX = 0, kStH1 = 40, kStH2 = 168, kStDP0 = 296, kStDL = 424;
+constexpr int kStageStride = 440;   // stored row; the logit-gradient block is 16 wide (3 used, rest zero)
+constexpr int kStDP1 = kStageStride;   // LDS copy only (128 floats)
 
 // scan.hip
 size_t scan_tmp_elems(int64_t n);
@@ -128,7 +132,7 @@ constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 *
 void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
                                hipStream_t s);
 void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
-void launch_weight_grads(const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
+void launch_weight_grads(const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
 // brick-tile accumulation of the feature and density gradients written by the
 // MLP backward and the compositing adjoint, then their addition to the grids
 void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
