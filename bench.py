@@ -78,10 +78,10 @@ def camera(W, H, pose):
 # passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
 # sources they were taken on (sha256 prefix of mlp.hip + mlp_common.h +
 # common.h + kernels.h).
-MLP_TRAFFIC_BYTES = 2.507e9 + 0.718e9
-MLP_TRAFFIC_SRC = "567d182017db1bc4"
+MLP_TRAFFIC_BYTES = 2.505e9 + 0.718e9
+MLP_TRAFFIC_SRC = "1bc9915fc79b2cbc"
 # L2 hit rate of the same launch (TCC_HIT / (TCC_HIT + TCC_MISS)), same passes
-MLP_L2_HIT = 0.853
+MLP_L2_HIT = 0.854
 # feature bytes a sample's gather requests from the grid in the MLP kernel:
 # 8 vertices x 12 channels x 4 B (the density is gathered by the march)
 GATHER_BYTES_PER_SAMPLE = 8 * 12 * 4
