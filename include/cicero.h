@@ -21,6 +21,10 @@
  *    zeroes them.
  *  - Calls that share a workspace must not overlap (same stream, or
  *    ordered by the caller).
+ *  - The library keeps no HIP object (stream, event) from one call to the
+ *    next: the streams it runs on are the caller's, and the events it needs
+ *    live for one call.  The only exception is the benchmark timing hooks
+ *    while they are enabled (cic_timing_enable).
  *
  * Data layout:
  *  - Grid: vertices on the corners of the box [box_lo, box_hi] ("align
@@ -251,20 +255,22 @@ enum { CIC_SEQ_OVERLAP = 1, CIC_SEQ_TEMPORAL = 2 };
  * only the poses known when window w starts; lead < 0 selects the paper's
  * t_r = window/2 frame intervals.  References use the intrinsics of
  * cams[s_w].
- * flags & CIC_SEQ_OVERLAP: references render on a second stream owned by
- * the library (one per device, default priority), concurrently with the
- * previous window's targets (Fig. 8); the work stays ordered after
- * everything issued to `stream` before the call, and `stream` waits for all
- * of it before any later work.  Without the flag everything runs on
- * `stream`, R_{w+1} after window w (Fig. 7a).  Both give identical results.
- * target_cus_per_xcd > 0 (with CIC_SEQ_OVERLAP) partitions the chip as the
- * paper splits the work between two engines: targets run on a library
- * stream restricted to that many CUs of each XCD and references on a stream
- * restricted to the rest (CU-masked streams, default priority, created once
- * per device and split); the persistent kernels are sized to their share.
- * Must be below the CUs per XCD (a multiple of 4 splits every shader
- * engine evenly); 0 shares the whole chip.  Results are identical in every
- * mode.
+ * flags & CIC_SEQ_OVERLAP: references render on `ref_stream` (a second
+ * stream the caller owns, default priority, not `stream`) concurrently with
+ * the previous window's targets on `stream` (Fig. 8); the reference work
+ * stays ordered after everything issued to `stream` before the call, and
+ * `stream` waits for all of it before any later work.  The events that
+ * order the two streams are created by the call and destroyed before it
+ * returns.  Without the flag everything runs on `stream`, R_{w+1} after
+ * window w (Fig. 7a), and ref_stream is not used (may be NULL).  Both give
+ * identical results.
+ * target_cus_per_xcd > 0 (with CIC_SEQ_OVERLAP) states that the chip is
+ * partitioned as the paper splits the work between two engines: `stream`
+ * is restricted to that many CUs of each XCD and `ref_stream` to the rest,
+ * as made by cic_stream_create_cu_masked with roles 0 and 1; the persistent
+ * kernels are sized to each share.  Must be below the CUs per XCD (a
+ * multiple of 4 splits every shader engine evenly); 0 means both streams
+ * may use the whole chip.  Results are identical in every mode.
  * cams: host array of n_frames cameras, all of one size with width*height
  * <= 2^21.  Outputs (device, frame-major): rgb [n_frames][H*W][3],
  * depth_z [n_frames][H*W], mask [n_frames][H*W] (1 = pixel rendered; all of
@@ -284,7 +290,19 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
                     int32_t target_cus_per_xcd,
                     float *rgb, float *depth_z, uint8_t *mask, int64_t *n_masked,
                     float *ref_c2w, int64_t *n_eval,
-                    void *ws, size_t ws_bytes, cic_stream_t stream);
+                    void *ws, size_t ws_bytes, cic_stream_t stream, cic_stream_t ref_stream);
+
+/* The two streams of render_sequence's CU-partitioned overlap (the paper's
+ * split of reference and target rendering between two engines, Sec. III-C
+ * and Fig. 8, on one GPU): a stream of the current device restricted to
+ * target_cus_per_xcd CUs of each XCD (role 0, targets) or to the remaining
+ * CUs (role 1, references), default priority.  The caller owns it and
+ * releases it with cic_stream_destroy (which waits for its work to finish)
+ * before the HIP runtime shuts down.  Errors: CIC_ERR_INVALID for a role
+ * other than 0/1 or a count outside [1, CUs per XCD - 1], CIC_ERR_HIP if the
+ * runtime refuses; *out is NULL on error. */
+int cic_stream_create_cu_masked(int32_t target_cus_per_xcd, int32_t role, cic_stream_t *out);
+int cic_stream_destroy(cic_stream_t stream);
 
 /* DS-s comparison variant of the paper's evaluation (Sec. VI-B, DS-2):
  * render the frame at 1/factor resolution -- same pose, ceil(W/s) x ceil(H/s)
@@ -318,7 +336,9 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
  * the launch stream.  cic_timing_read waits for the recorded events and
  * writes, per stage, the summed milliseconds and the number of launches
  * since the last enable; it fills at most n_stages entries of each array
- * (host pointers).  Stages: */
+ * (host pointers).  Every cic_timing_enable call destroys the events of the
+ * calling thread, so after cic_timing_enable(0) the library holds no HIP
+ * object for it; call that before the HIP runtime shuts down.  Stages: */
 enum {
     CIC_STAGE_MARCH = 0,      /* ray march + transmittance scan */
     CIC_STAGE_COMPACT = 1,    /* count scan, compaction, voxel bucketing */

@@ -6,6 +6,7 @@ non-zero return code.  No arithmetic of the method happens here; there is no
 CPU fallback: if the library is missing or the device is not gfx950 the
 calls raise.
 """
+import atexit
 import ctypes as C
 import os
 import threading
@@ -56,7 +57,7 @@ class Camera(C.Structure):
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
            "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
            "cic_timing_read", "cic_extrapolate_pose", "cic_relative_pose", "render_sequence", "cic_timing_frames",
-           "render_frame_ds"]
+           "render_frame_ds", "cic_stream_create_cu_masked", "cic_stream_destroy"]
 STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad", "embed"]
 
 _lib = None
@@ -90,13 +91,33 @@ def lib():
                 L.cic_extrapolate_pose.argtypes = [vp, vp, f, vp]
                 L.cic_relative_pose.argtypes = [vp, vp, vp]
                 L.render_sequence.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, f, C.c_int32, C.c_int32, vp,
-                                              vp, vp, vp, vp, vp, vp, u64, vp]
+                                              vp, vp, vp, vp, vp, vp, u64, vp, vp]
+                L.cic_stream_create_cu_masked.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+                L.cic_stream_destroy.argtypes = [vp]
                 L.cic_timing_frames.argtypes = [vp, C.c_int]
                 L.render_frame_ds.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, u64, vp]
                 for name in EXPORTS[2:]:
                     getattr(L, name).restype = C.c_int
                 _lib = L
+                atexit.register(release)
     return _lib
+
+
+def release():
+    """Destroy every HIP object the binding holds for the library: the
+    CU-partitioned stream pairs and the timing events.  Registered to run at
+    interpreter exit, while the HIP runtime is still up; safe to call
+    again."""
+    if _lib is None:
+        return
+    with _lock:
+        pairs = list(_cu_streams.items())
+        _cu_streams.clear()
+    for (dev, _t), (s_tgt, s_ref) in pairs:
+        with torch.cuda.device(dev):
+            _lib.cic_stream_destroy(s_tgt)
+            _lib.cic_stream_destroy(s_ref)
+    _lib.cic_timing_enable(0)
 
 
 def last_error():
@@ -286,9 +307,52 @@ def relative_pose(c2w_ref, c2w_tgt):
     return list(out)
 
 
+# CU-partitioned stream pairs (target, reference) per (device, CUs per XCD),
+# created on first use and destroyed by release(); a plain second stream for
+# the shared-chip overlap is a torch stream per device.
+_cu_streams = {}
+_side_streams = {}
+
+
+def cu_streams(target_cus_per_xcd, device=None):
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    key = (dev, int(target_cus_per_xcd))
+    with _lock:
+        pair = _cu_streams.get(key)
+    if pair is None:
+        out = []
+        with torch.cuda.device(dev):
+            for role in (0, 1):
+                h = C.c_void_p()
+                rc = lib().cic_stream_create_cu_masked(C.c_int32(target_cus_per_xcd), C.c_int32(role), C.byref(h))
+                if rc != 0:
+                    for s in out:
+                        lib().cic_stream_destroy(s)
+                    raise CicError(rc, last_error())
+                out.append(h)
+        pair = (out[0], out[1])
+        with _lock:
+            _cu_streams[key] = pair
+    return pair
+
+
+def side_stream(device=None):
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    with _lock:
+        st = _side_streams.get(dev)
+        if st is None:
+            st = torch.cuda.Stream(device=dev)
+            _side_streams[dev] = st
+    return st
+
+
 def render_sequence(grid, mlp, opts, cams, window, lead, flags, rgb, depth_z, mask, n_masked=None, n_eval=None,
                     target_cus_per_xcd=0):
-    """cams: sequence of Camera structs; returns the reference poses."""
+    """cams: sequence of Camera structs; returns the reference poses.  With
+    CIC_SEQ_OVERLAP the references run on a second stream (a torch stream, or
+    with target_cus_per_xcd > 0 the CU-masked pair, targets on the first);
+    the call is ordered after earlier work on the current stream and later
+    work on it waits for the whole sequence."""
     n = len(cams)
     arr = (Camera * max(n, 1))(*cams)
     n_win = (n - 1 + window - 1) // window if n > 1 and window > 0 else 0
@@ -296,10 +360,26 @@ def render_sequence(grid, mlp, opts, cams, window, lead, flags, rgb, depth_z, ma
     npix = cams[0].width * cams[0].height if n else 0
     nb = workspace_bytes(OP_RENDER_SEQUENCE, npix, grid, opts)
     ws = workspace(nb, rgb.device)
+    cur = torch.cuda.current_stream(rgb.device)
+    s_tgt, s_ref = C.c_void_p(cur.cuda_stream), None
+    masked = None
+    if flags & CIC_SEQ_OVERLAP:
+        if target_cus_per_xcd > 0:
+            pair = cu_streams(target_cus_per_xcd, rgb.device)
+            s_tgt, s_ref = pair
+            masked = torch.cuda.ExternalStream(pair[0].value, device=rgb.device)
+        else:
+            s_ref = C.c_void_p(side_stream(rgb.device).cuda_stream)
+    if masked is not None:
+        # the target stream starts after the caller's earlier work
+        masked.wait_stream(cur)
     _check(lib().render_sequence(C.byref(grid), C.byref(mlp), C.byref(opts), arr, C.c_int32(n), C.c_int32(window),
                                  C.c_float(lead), C.c_int32(flags), C.c_int32(target_cus_per_xcd), _ptr(rgb),
                                  _ptr(depth_z), _ptr(mask),
-                                 _ptr(n_masked), refs, _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()), _stream()))
+                                 _ptr(n_masked), refs, _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()), s_tgt, s_ref))
+    if masked is not None:
+        # the caller's later work waits for the whole sequence
+        cur.wait_stream(masked)
     return [list(refs[12 * i:12 * i + 12]) for i in range(max(n_win - 1, 0))]
 
 

@@ -493,54 +493,48 @@ void sparw_frame(const cic_grid *grid, const GridK &gk, const cic_mlp *mlp, cons
     if (n_masked) launch_sparw_finish(w.n_holes, n_masked, s);
 }
 
-// The library's second stream per device (default priority, non-blocking)
-// and the events that order it against the caller's stream.
-struct SideSync {
-    bool ready = false;
-    hipStream_t stream = nullptr;
+// Events that order render_sequence's two streams.  They live for one call:
+// created at its start and destroyed before it returns (HIP keeps a
+// destroyed event's pending record and waits alive until they complete).
+struct SeqEvents {
     hipEvent_t start = nullptr, side_end = nullptr, f0 = nullptr, win_end[2] = {}, ref_ready[2] = {};
+    hipEvent_t *all(int i)
+    {
+        hipEvent_t *evs[] = {&start, &side_end, &f0, &win_end[0], &win_end[1], &ref_ready[0], &ref_ready[1]};
+        return evs[i];
+    }
+    static constexpr int kCount = 7;
+    int create()
+    {
+        for (int i = 0; i < kCount; ++i)
+            if (hipEventCreateWithFlags(all(i), hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                destroy();
+                return fail(CIC_ERR_HIP, "could not create the sequence's events");
+            }
+        return CIC_OK;
+    }
+    void destroy()
+    {
+        for (int i = 0; i < kCount; ++i)
+            if (*all(i)) {
+                (void)hipEventDestroy(*all(i));
+                *all(i) = nullptr;
+            }
+    }
+    ~SeqEvents() { destroy(); }
 };
-std::mutex g_side_mu;
-SideSync g_side[64];
 
-int side_sync(SideSync **out)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
-        (void)hipGetLastError();
-        return fail(CIC_ERR_HIP, "no HIP device");
-    }
-    std::lock_guard<std::mutex> lk(g_side_mu);
-    SideSync &x = g_side[dev];
-    if (!x.ready) {
-        bool good = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking) == hipSuccess;
-        hipEvent_t *evs[] = {&x.start, &x.side_end, &x.f0, &x.win_end[0], &x.win_end[1], &x.ref_ready[0],
-                             &x.ref_ready[1]};
-        for (hipEvent_t *e : evs) good = good && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
-        if (!good) {
-            (void)hipGetLastError();
-            return fail(CIC_ERR_HIP, "could not create the reference stream or its events");
-        }
-        x.ready = true;
-    }
-    *out = &x;
-    return CIC_OK;
-}
-
-// CU-partitioned stream pair for render_sequence: per XCD, `t` CUs for the
-// targets and the rest for the references.  The HIP runtime spreads the bits of a
-// stream's CU mask over the chip interleaved: bit i goes to XCD i % 8, and
-// within the XCD bit i / 8 goes to shader engine (i / 8) % 4.  The targets
-// take bits [0, 8t) and the references the rest, so every XCD gets t target
-// CUs, and with t a multiple of 4 every shader engine gets the same number
-// (the dispatcher deals workgroups to the shader engines in turn, so an
-// uneven split would leave the persistent kernels' last workgroups waiting).
+// CU masks for render_sequence's partitioned overlap: per XCD, `t` CUs for
+// the targets and the rest for the references.  The HIP runtime spreads the
+// bits of a stream's CU mask over the chip interleaved: bit i goes to XCD
+// i % 8, and within the XCD bit i / 8 goes to shader engine (i / 8) % 4.
+// The targets take bits [0, 8t) and the references the rest, so every XCD
+// gets t target CUs, and with t a multiple of 4 every shader engine gets the
+// same number (the dispatcher deals workgroups to the shader engines in
+// turn, so an uneven split would leave the persistent kernels' last
+// workgroups waiting).
 constexpr int kXcdCount = 8;
-struct PartStreams {
-    int t = 0;
-    hipStream_t tgt = nullptr, ref = nullptr;
-};
-std::vector<PartStreams> g_part[64];
 
 int device_cus(int *n)
 {
@@ -554,33 +548,32 @@ int device_cus(int *n)
     return CIC_OK;
 }
 
-int part_streams(int t, PartStreams *out)
+int check_partition(int t, int *ncu_out)
 {
-    int dev = 0, ncu = 0, rc;
+    int ncu = 0, rc;
     if ((rc = device_cus(&ncu))) return rc;
-    (void)hipGetDevice(&dev);
     const int per = ncu / kXcdCount;
     if (ncu % kXcdCount != 0 || per % kXcdCount != 0 || ncu > 1024)
         return fail(CIC_ERR_INVALID, "CU partitioning needs 8 XCDs of a multiple of 8 CUs (device has %d CUs)", ncu);
     if (t < 1 || t >= per) return fail(CIC_ERR_INVALID, "target_cus_per_xcd=%d outside [1,%d]", t, per - 1);
-    std::lock_guard<std::mutex> lk(g_side_mu);
-    for (auto &p : g_part[dev])
-        if (p.t == t) {
-            *out = p;
-            return CIC_OK;
-        }
-    uint32_t mt[32] = {}, mr[32] = {};
-    for (int bit = 0; bit < ncu; ++bit) (bit < kXcdCount * t ? mt : mr)[bit / 32] |= 1u << (bit % 32);
-    PartStreams p;
-    p.t = t;
-    const uint32_t words = (uint32_t)((ncu + 31) / 32);
-    if (hipExtStreamCreateWithCUMask(&p.tgt, words, mt) != hipSuccess ||
-        hipExtStreamCreateWithCUMask(&p.ref, words, mr) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CIC_ERR_HIP, "could not create CU-masked streams");
-    }
-    g_part[dev].push_back(p);
-    *out = p;
+    *ncu_out = ncu;
+    return CIC_OK;
+}
+
+int check_warp_args(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12], const float *ref_rgb,
+                    const float *ref_depth_z, float max_angle_deg, const float *tgt_rgb, const float *tgt_depth_z,
+                    const uint8_t *mask)
+{
+    int rc;
+    if ((rc = check_camera(ref, "reference")) || (rc = check_camera(tgt, "target"))) return rc;
+    if (!finite_f(max_angle_deg) || max_angle_deg < 0.f || max_angle_deg > 180.f)
+        return fail(CIC_ERR_INVALID, "max_angle_deg must be in [0, 180]");
+    if (!ref_T_tgt) return fail(CIC_ERR_INVALID, "ref_T_tgt is NULL");
+    for (int i = 0; i < 12; ++i)
+        if (!finite_f(ref_T_tgt[i])) return fail(CIC_ERR_INVALID, "ref_T_tgt is not finite");
+    if ((int64_t)ref->width * ref->height > 0xffffffffll) return fail(CIC_ERR_INVALID, "reference too large");
+    if (!ref_rgb || !ref_depth_z || !tgt_rgb || !tgt_depth_z || !mask)
+        return fail(CIC_ERR_INVALID, "frame pointer is NULL");
     return CIC_OK;
 }
 
@@ -706,15 +699,8 @@ int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_t
                int32_t *src_index, void *ws, size_t ws_bytes, cic_stream_t stream)
 {
     int rc;
-    if ((rc = check_camera(ref, "reference")) || (rc = check_camera(tgt, "target"))) return rc;
-    if (!finite_f(max_angle_deg) || max_angle_deg < 0.f || max_angle_deg > 180.f)
-        return fail(CIC_ERR_INVALID, "max_angle_deg must be in [0, 180]");
-    if (!ref_T_tgt) return fail(CIC_ERR_INVALID, "ref_T_tgt is NULL");
-    for (int i = 0; i < 12; ++i)
-        if (!finite_f(ref_T_tgt[i])) return fail(CIC_ERR_INVALID, "ref_T_tgt is not finite");
-    if ((int64_t)ref->width * ref->height > 0xffffffffll) return fail(CIC_ERR_INVALID, "reference too large");
-    if (!ref_rgb || !ref_depth_z || !tgt_rgb || !tgt_depth_z || !mask)
-        return fail(CIC_ERR_INVALID, "frame pointer is NULL");
+    if ((rc = check_warp_args(ref, tgt, ref_T_tgt, ref_rgb, ref_depth_z, max_angle_deg, tgt_rgb, tgt_depth_z, mask)))
+        return rc;
     const int64_t np = (int64_t)tgt->width * tgt->height;
     Carver m(nullptr);
     carve_warp(m, np, false);
@@ -766,7 +752,7 @@ int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts 
 int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *cams,
                     int32_t n_frames, int32_t window, float lead, int32_t flags, int32_t target_cus_per_xcd,
                     float *rgb, float *depth_z, uint8_t *mask, int64_t *n_masked, float *ref_c2w, int64_t *n_eval,
-                    void *ws, size_t ws_bytes, cic_stream_t stream)
+                    void *ws, size_t ws_bytes, cic_stream_t stream, cic_stream_t ref_stream)
 {
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_mlp(mlp)) || (rc = check_opts(opts, grid))) return rc;
@@ -780,6 +766,8 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
         return fail(CIC_ERR_INVALID, "CIC_SEQ_TEMPORAL cannot be combined with CIC_SEQ_OVERLAP");
     if (target_cus_per_xcd < 0 || (target_cus_per_xcd > 0 && !(flags & CIC_SEQ_OVERLAP)))
         return fail(CIC_ERR_INVALID, "target_cus_per_xcd needs CIC_SEQ_OVERLAP and must be >= 0");
+    if ((flags & CIC_SEQ_OVERLAP) && (!ref_stream || ref_stream == stream))
+        return fail(CIC_ERR_INVALID, "CIC_SEQ_OVERLAP needs a reference stream other than the target stream");
     if (!cams) return fail(CIC_ERR_INVALID, "cams is NULL");
     for (int32_t k = 0; k < n_frames; ++k) {
         if ((rc = check_camera(&cams[k], "sequence"))) return rc;
@@ -840,23 +828,20 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     }
 
     const bool overlap = (flags & CIC_SEQ_OVERLAP) != 0;
-    SideSync *ss = nullptr;
-    if (overlap && (rc = side_sync(&ss))) return rc;
-    PartStreams ps;
-    if (target_cus_per_xcd > 0 && (rc = part_streams(target_cus_per_xcd, &ps))) return rc;
     const bool part = target_cus_per_xcd > 0;
-    hipStream_t caller = (hipStream_t)stream;
-    // s: targets, sb: references
-    hipStream_t s = part ? ps.tgt : caller;
-    hipStream_t sb = part ? ps.ref : (overlap ? ss->stream : caller);
+    int ncu = 0;
+    if (part && (rc = check_partition(target_cus_per_xcd, &ncu))) return rc;
+    // s: targets (the caller's stream), sb: references
+    hipStream_t s = (hipStream_t)stream;
+    hipStream_t sb = overlap ? (hipStream_t)ref_stream : s;
+    SeqEvents ev;
+    if (overlap && (rc = ev.create())) return rc;
     const bool voxel = opts->order == CIC_ORDER_VOXEL;
     const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
     const OptsK ok_ = make_optsk(opts);
     Carver cv(align_ws(ws));
     SeqBufs q = carve_seq(cv, np, opts, n_bricks_of(grid));
     if (part) {
-        int ncu = 0;
-        if ((rc = device_cus(&ncu))) return rc;
         q.a.grid_cus = kXcdCount * target_cus_per_xcd;
         q.b.grid_cus = ncu - q.a.grid_cus;
     }
@@ -869,30 +854,29 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     if (g_timing.on) {
         g_timing.reset_frames();
         g_timing.frame0 = g_timing.get();
-        if (g_timing.frame0) (void)hipEventRecord(g_timing.frame0, caller);
+        if (g_timing.frame0) (void)hipEventRecord(g_timing.frame0, s);
     }
     if (overlap) {
-        (void)hipEventRecord(ss->start, caller);
-        (void)hipStreamWaitEvent(sb, ss->start, 0);
-        if (part) (void)hipStreamWaitEvent(s, ss->start, 0);
+        (void)hipEventRecord(ev.start, s);
+        (void)hipStreamWaitEvent(sb, ev.start, 0);
     }
     // frame 0: rendered in full; it is R_0
     full_frame(grid, gk, mlp, ok_, voxel, q.a, cams[0], rgb, depth_z, n_eval, s);
     launch_fill_u8(mask, 1, np, s);
     if (n_masked) launch_fill_u64((uint64_t *)n_masked, (uint64_t)np, 1, s);
     frame_mark(s);
-    if (overlap) (void)hipEventRecord(ss->f0, s);
+    if (overlap) (void)hipEventRecord(ev.f0, s);
 
     for (int32_t w = 0; w < n_win; ++w) {
         if (overlap) {
-            // R_{w+1} renders on the side stream once the poses it needs are known (the frames
-            // before window w are done); its slot was last read by window w - 1.
+            // R_{w+1} renders on the reference stream once the poses it needs are known (the
+            // frames before window w are done); its slot was last read by window w - 1.
             if (w + 1 < n_win) {
-                (void)hipStreamWaitEvent(sb, w == 0 ? ss->f0 : ss->win_end[(w - 1) & 1], 0);
+                (void)hipStreamWaitEvent(sb, w == 0 ? ev.f0 : ev.win_end[(w - 1) & 1], 0);
                 render_ref(w + 1, sb);
-                (void)hipEventRecord(ss->ref_ready[(w + 1) & 1], sb);
+                (void)hipEventRecord(ev.ref_ready[(w + 1) & 1], sb);
             }
-            if (w >= 1) (void)hipStreamWaitEvent(s, ss->ref_ready[w & 1], 0);
+            if (w >= 1) (void)hipStreamWaitEvent(s, ev.ref_ready[w & 1], 0);
         } else if (w >= 1) {
             render_ref(w, s);
         }
@@ -907,16 +891,12 @@ int render_sequence(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
                         n_eval, s);
             frame_mark(s);
         }
-        if (overlap) (void)hipEventRecord(ss->win_end[w & 1], s);
+        if (overlap) (void)hipEventRecord(ev.win_end[w & 1], s);
     }
     if (overlap) {
-        (void)hipEventRecord(ss->side_end, sb);
-        (void)hipStreamWaitEvent(caller, ss->side_end, 0);
-        if (part) {
-            // the target stream's last work, reusing the first window's end event
-            (void)hipEventRecord(ss->win_end[0], s);
-            (void)hipStreamWaitEvent(caller, ss->win_end[0], 0);
-        }
+        // the caller's stream waits for the references' last work
+        (void)hipEventRecord(ev.side_end, sb);
+        (void)hipStreamWaitEvent(s, ev.side_end, 0);
     }
     return after_launch("render_sequence");
 }
@@ -1042,13 +1022,46 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
 
 int cic_timing_enable(int on)
 {
+    // every event recorded so far is destroyed: while timing is off the
+    // library holds no HIP object
     for (auto &r : g_timing.recs) {
-        g_timing.pool.push_back(r.a);
-        g_timing.pool.push_back(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     g_timing.recs.clear();
     g_timing.reset_frames();
+    for (auto e : g_timing.pool) (void)hipEventDestroy(e);
+    g_timing.pool.clear();
     g_timing.on = on != 0;
+    return ok();
+}
+
+int cic_stream_create_cu_masked(int32_t target_cus_per_xcd, int32_t role, cic_stream_t *out)
+{
+    if (!out) return fail(CIC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (role != 0 && role != 1) return fail(CIC_ERR_INVALID, "role=%d; 0 = targets, 1 = references", role);
+    int rc, ncu = 0;
+    if ((rc = check_device()) || (rc = check_partition(target_cus_per_xcd, &ncu))) return rc;
+    uint32_t mask[32] = {};
+    for (int bit = 0; bit < ncu; ++bit)
+        if ((bit < kXcdCount * target_cus_per_xcd) == (role == 0)) mask[bit / 32] |= 1u << (bit % 32);
+    hipStream_t st = nullptr;
+    if (hipExtStreamCreateWithCUMask(&st, (uint32_t)((ncu + 31) / 32), mask) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "could not create a CU-masked stream");
+    }
+    *out = (cic_stream_t)st;
+    return ok();
+}
+
+int cic_stream_destroy(cic_stream_t stream)
+{
+    if (!stream) return ok();
+    if (hipStreamDestroy((hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "hipStreamDestroy failed");
+    }
     return ok();
 }
 

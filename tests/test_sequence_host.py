@@ -79,10 +79,11 @@ def test_render_sequence_validation(L):
     p = C.c_void_p(0x5000)
     big = C.c_size_t(1 << 40)
 
-    def call(n=2, window=4, lead=-1.0, flags=1, cams_=cams, ws_bytes=big, part=0):
+    def call(n=2, window=4, lead=-1.0, flags=1, cams_=cams, ws_bytes=big, part=0, stream=None,
+             ref=C.c_void_p(0x7000)):
         return lib.render_sequence(C.byref(g), C.byref(m), C.byref(o), cams_, C.c_int32(n), C.c_int32(window),
                                    C.c_float(lead), C.c_int32(flags), C.c_int32(part), p, p, p, None, None, None, p,
-                                   ws_bytes, None)
+                                   ws_bytes, stream, ref)
 
     assert call(n=0) == 0
     assert call(window=0) == -1 and "window" in L.last_error()
@@ -94,5 +95,19 @@ def test_render_sequence_validation(L):
     assert call(n=-1) == -1
     assert call(part=4, flags=0) == -1 and "target_cus_per_xcd" in L.last_error()
     assert call(part=-1) == -1
+    # the overlapped schedule needs a caller-owned reference stream distinct from the target stream
+    assert call(ref=None) == -1 and "reference stream" in L.last_error()
+    assert call(stream=C.c_void_p(0x7000)) == -1 and "reference stream" in L.last_error()
     per_frame = L.workspace_bytes(L.OP_RENDER_SEQUENCE, 1024, g, o)
     assert per_frame > 2 * L.workspace_bytes(L.OP_RENDER_FRAME, 1024, g, o)
+
+
+def test_cu_masked_stream_validation(L):
+    """cic_stream_create_cu_masked rejects bad arguments before touching the
+    runtime, and destroying a NULL stream is a no-op."""
+    lib = L.lib()
+    h = C.c_void_p(0x1234)
+    assert lib.cic_stream_create_cu_masked(C.c_int32(8), C.c_int32(2), C.byref(h)) == -1
+    assert h.value is None and "role" in L.last_error()
+    assert lib.cic_stream_create_cu_masked(C.c_int32(8), C.c_int32(0), None) == -1
+    assert lib.cic_stream_destroy(None) == 0
