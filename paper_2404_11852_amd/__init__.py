@@ -170,21 +170,50 @@ def render_backward(model, opts, rays_o, rays_d, d_rgb, d_depth_t=None, d_acc=No
     return grads
 
 
+class _Bound:
+    """Grid and MLP descriptors built from given tensors (the autograd
+    leaves), with the occupancy, box and shift of a model."""
+
+    def __init__(self, model, density, features, w):
+        for t in (density, features, *w.values()):
+            if t.device != model.density.device or t.dtype != torch.float32 or not t.is_contiguous():
+                raise CicError(-1, "RenderRays takes contiguous float32 tensors on the model's device")
+        if density.shape != model.density.shape or features.shape != model.features.shape:
+            raise CicError(-1, "RenderRays: grid shapes differ from the model's")
+        for k, v in w.items():
+            if v.shape != model.w[k].shape:
+                raise CicError(-1, "RenderRays: %s has shape %s, the model's %s" % (k, tuple(v.shape),
+                                                                                   tuple(model.w[k].shape)))
+        self.device = model.device
+        self.hash = None
+        self.density, self.features, self.w = density, features, w
+        self.grid = _lib.make_grid(density, features, model.occupancy, model.box_lo, model.box_hi,
+                                   model.density_shift)
+        self.mlp = _lib.make_mlp(w, CIC_F32)
+
+
 class RenderRays(torch.autograd.Function):
     """rgb, depth_t, acc = RenderRays.apply(density, features, w0, b0, w1, b1,
-    w2, b2, rays_o, rays_d, model, opts).  The forward keeps only its inputs;
-    the backward recomputes each ray inside render_backward."""
+    w2, b2, rays_o, rays_d, model, opts).  Renders with the tensors passed
+    in (float32, contiguous, on the model's device, the model's shapes); the
+    model supplies the occupancy, box and density shift.  The forward keeps
+    only its inputs; the backward recomputes each ray inside
+    render_backward."""
 
     @staticmethod
     def forward(ctx, density, features, w0, b0, w1, b1, w2, b2, rays_o, rays_d, model, opts):
-        ctx.model, ctx.opts = model, opts
-        ctx.save_for_backward(rays_o, rays_d)
-        return render_rays(model, opts, rays_o, rays_d)
+        if model.hash is not None:
+            raise CicError(-1, "RenderRays does not support the multi-level encoding")
+        bound = _Bound(model, density, features, {"w0": w0, "b0": b0, "w1": w1, "b1": b1, "w2": w2, "b2": b2})
+        ctx.bound, ctx.opts = bound, opts
+        ctx.save_for_backward(density, features, w0, b0, w1, b1, w2, b2, rays_o, rays_d)
+        return render_rays(bound, opts, rays_o, rays_d)
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_acc):
-        rays_o, rays_d = ctx.saved_tensors
-        g = render_backward(ctx.model, ctx.opts, rays_o, rays_d, g_rgb,
+        saved = ctx.saved_tensors   # raises if a leaf was modified in place since the forward
+        rays_o, rays_d = saved[8], saved[9]
+        g = render_backward(ctx.bound, ctx.opts, rays_o, rays_d, g_rgb,
                             None if g_depth is None else g_depth, None if g_acc is None else g_acc)
         return (g["density"], g["features"], g["w0"], g["b0"], g["w1"], g["b1"], g["w2"], g["b2"],
                 None, None, None, None)

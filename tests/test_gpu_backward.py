@@ -148,6 +148,48 @@ def test_autograd_function_matches_direct_call():
         assert torch.allclose(leaf.grad, ref, rtol=1e-5, atol=1e-7 * float(ref.abs().max()) + 1e-12), k
 
 
+def test_autograd_function_uses_the_leaves_it_is_given():
+    """RenderRays renders with the tensors passed in, not the model's own
+    copies: after an SGD step on the leaves, the next forward equals a plain
+    render of a model holding the updated values (same bits), its gradients
+    equal render_backward on that model, and a leaf modified in place
+    between forward and backward is refused."""
+    import paper_2404_11852_amd as cic
+    print_case("autograd leaves updated between calls")
+    p = Pair(16, seed=6, mlp_seed=7, bias_std=0.1)
+    o, d = synth.random_rays(400, seed=11)
+    to_, td = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    go = cic.make_opts(48)
+    params = [p.gpu.density, p.gpu.features] + [p.gpu.w[k] for k in ("w0", "b0", "w1", "b1", "w2", "b2")]
+    leaves = [t.detach().clone().requires_grad_(True) for t in params]
+    target = torch.rand((400, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    rgb0, _, _ = cic.RenderRays.apply(*leaves, to_, td, p.gpu, go)
+    ((rgb0 - target) ** 2).mean().backward()
+    with torch.no_grad():
+        for t in leaves:
+            t -= 50.0 * t.grad
+            t.grad = None
+    rgb1, dep1, acc1 = cic.RenderRays.apply(*leaves, to_, td, p.gpu, go)
+    assert float((rgb1 - rgb0).abs().max()) > 1e-4      # the step changed the image
+    fresh = cic.Model(leaves[0].detach().cpu().numpy(), leaves[1].detach().cpu().numpy(),
+                      {k: leaves[2 + i].detach().cpu().numpy() for i, k in enumerate(NAMES[2:])},
+                      device="cuda", density_shift=synth.DENSITY_SHIFT)
+    ref_rgb, ref_dep, ref_acc = cic.render_rays(fresh, go, to_, td)
+    assert torch.equal(rgb1, ref_rgb) and torch.equal(dep1, ref_dep) and torch.equal(acc1, ref_acc)
+    loss = ((rgb1 - target) ** 2).mean()
+    loss.backward()
+    d_rgb = (2.0 * (rgb1.detach() - target) / rgb1.numel()).contiguous()
+    g = cic.render_backward(fresh, go, to_, td, d_rgb)
+    for leaf, k in zip(leaves, NAMES):
+        ref = g[k]
+        assert torch.allclose(leaf.grad, ref, rtol=1e-5, atol=1e-7 * float(ref.abs().max()) + 1e-12), k
+    rgb2, _, _ = cic.RenderRays.apply(*leaves, to_, td, p.gpu, go)
+    with torch.no_grad():
+        leaves[3].add_(1.0)
+    with pytest.raises(RuntimeError):
+        ((rgb2 - target) ** 2).mean().backward()
+
+
 def test_backward_degenerate_inputs():
     """No rays, and rays that all miss the grid (no live samples, so no brick
     segments): the accumulated gradients stay exactly zero; a zero upstream
