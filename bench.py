@@ -29,11 +29,12 @@ METRIC = "ray samples/s + 800x800 FPS (full vs SpaRW); fwd+bwd samples/s; BF16 v
 MLP_FLOP_PER_SAMPLE = 2 * (12 * 128 + 128 * 128 + 128 * 3)   # 36,608 useful FLOP
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# Training step, per evaluated sample, on FP32 MFMA: the forward render (as
-# above), the adjoint's recomputed forward on the full 39-wide input, the MLP
-# backward (W1^T dp1 and the feature rows of W0^T dp0) and the weight
-# gradients (outer products of the three layers).
-STAGED_FWD_FLOP_PER_SAMPLE = 2 * (39 * 128 + 128 * 128 + 128 * 3)   # 43,520
+# Training step, per evaluated sample, the method's own work on FP32 MFMA:
+# the forward render (as above), the adjoint's forward recomputation (the
+# same 36,608 useful FLOP: the view-encoding part of layer 0 is per ray), the
+# MLP backward (W1^T dp1 and the feature rows of W0^T dp0) and the weight
+# gradients (outer products of the three layers): 152,576 FLOP per sample.
+RECOMPUTE_FLOP_PER_SAMPLE = MLP_FLOP_PER_SAMPLE                      # 36,608
 BWD_FLOP_PER_SAMPLE = 2 * (128 * 128 + 12 * 128)                     # 35,840
 WGRAD_FLOP_PER_SAMPLE = 2 * (128 * 39 + 128 * 128 + 3 * 128)        # 43,520
 # Compositing adjoint, algorithmic bytes per live sample: weight, colour and
@@ -391,20 +392,34 @@ def hash_bench(W, H, steps, dense_ms=None):
     return out
 
 
+AMB17_GOLDEN = os.path.join(ROOT, "tests", "golden", "amb17_reference.npz")
+
+
 def precision_bench(scene, occ, steps):
     """Eight 800x800 views on the radius-4 sphere in one render_rays call:
-    FP16 grids + BF16 MLP against the FP32 path on the same rays."""
+    FP16 grids + BF16 MLP against the FP32 path on the same rays.  Quality:
+    PSNR against the float64 oracle's converged reference G (1024 samples,
+    no skipping or termination) on 16,384 seeded pixels per view, from the
+    stored oracle colours in tests/golden/amb17_reference.npz (written by
+    make_amb17_reference.py), next to the oracle's own PSNR at the
+    workload's settings; margin = PSNR(G, BF16) - (PSNR(G, oracle) - 0.1 dB).
+    The two error sources are measured apart: FP16 grid with the FP32 MLP,
+    FP32 grid with the BF16 MLP."""
+    import numpy as np
     import torch
     import synth
     import paper_2404_11852_amd as cic
     from paper_2404_11852_amd import _lib
     dens, feats, mlp = scene
     W = H = 800
-    g16 = cic.Model(dens, feats, mlp, device="cuda:0", storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
-                    compute=cic.CIC_BF16)
-    g16.set_occupancy(occ)
-    g32 = cic.Model(dens, feats, mlp, device="cuda:0", density_shift=synth.DENSITY_SHIFT)
-    g32.set_occupancy(occ)
+    models = {}
+    for name, storage, compute in (("bf16", torch.float16, cic.CIC_BF16), ("fp32", torch.float32, cic.CIC_F32),
+                                   ("f32grid_bf16mlp", torch.float32, cic.CIC_BF16),
+                                   ("f16grid_f32mlp", torch.float16, cic.CIC_F32)):
+        m = cic.Model(dens, feats, mlp, device="cuda:0", storage=storage, density_shift=synth.DENSITY_SHIFT,
+                      compute=compute)
+        m.set_occupancy(occ)
+        models[name] = m
     f, cx, cy = synth.intrinsics(W, H)
     rays = [cic.generate_rays(cic.make_camera(W, H, f, cx, cy, synth.as_f32(p))) for p in synth.sphere_poses(8, 2)]
     o = torch.cat([r[0] for r in rays]).contiguous()
@@ -413,7 +428,8 @@ def precision_bench(scene, occ, steps):
     gv = cic.make_opts(256, 1e-4, True, order=cic.CIC_ORDER_VOXEL)
     out = {}
     imgs = {}
-    for name, model, go in (("bf16", g16, go), ("bf16_voxel", g16, gv), ("fp32", g32, go)):
+    for name, model, go in (("bf16", models["bf16"], go), ("bf16_voxel", models["bf16"], gv),
+                            ("fp32", models["fp32"], go)):
         cic.render_rays(model, go, o, d)
         n_eval = torch.zeros(1, dtype=torch.int64, device="cuda:0")
         torch.cuda.synchronize()
@@ -441,6 +457,29 @@ def precision_bench(scene, occ, steps):
             ach = MLP_FLOP_PER_SAMPLE * out[name]["evaluated_samples"] / (mlp_ms * 1e-3) / 1e12
             out[name + "_mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
                                            "frac": ach / 2500.0}
+    if os.path.exists(AMB17_GOLDEN):
+        gold = np.load(AMB17_GOLDEN)
+        pix = gold["pix"]
+        sel = torch.from_numpy((np.arange(pix.shape[0])[:, None] * (W * H) + pix).reshape(-1).astype(np.int64))
+        g = gold["g"].astype(np.float64)
+        o64 = gold["o64"].astype(np.float64)
+
+        def p_np(a, b):
+            mse = float(np.mean((a - b) ** 2))
+            return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+        cols = {"bf16": imgs["bf16_voxel"], "fp32": imgs["fp32"]}
+        for name in ("f32grid_bf16mlp", "f16grid_f32mlp"):
+            cols[name], _, _ = cic.render_rays(models[name], go, o, d)
+        q = {"pixels": int(sel.numel()), "psnr_G_oracle_db": p_np(g, o64)}
+        for name, img in cols.items():
+            v = img[sel.cuda()].double().cpu().numpy()
+            q["psnr_G_%s_db" % name] = p_np(g, v)
+            q["psnr_oracle_%s_db" % name] = p_np(o64, v)
+            q["max_abs_oracle_%s" % name] = float(np.abs(v - o64).max())
+        q["margin_db"] = q["psnr_G_bf16_db"] - (q["psnr_G_oracle_db"] - 0.1)
+        q["criterion"] = "PSNR(G, BF16) >= PSNR(G, oracle) - 0.1 dB"
+        out["quality_vs_converged"] = q
     out["workload"] = "8 views x 800x800 (5.12M rays, one call), 160^3 grid, 256 samples, skip + termination"
     return out
 
@@ -502,9 +541,10 @@ def fwd_bwd_bench(steps):
            "workload": "8192 rays from 8 views, 160^3 model grids N(0,0.01), 256 samples, fwd + adjoint, FP32"}
     mfma_ms = sum(sm.get(k, 0.0) for k in ("mlp", "bwd_mlp", "bwd_wgrad"))
     if mfma_ms > 0:
-        flop = (MLP_FLOP_PER_SAMPLE + STAGED_FWD_FLOP_PER_SAMPLE + BWD_FLOP_PER_SAMPLE + WGRAD_FLOP_PER_SAMPLE) * ne
+        flop = (MLP_FLOP_PER_SAMPLE + RECOMPUTE_FLOP_PER_SAMPLE + BWD_FLOP_PER_SAMPLE + WGRAD_FLOP_PER_SAMPLE) * ne
         ach = flop / (mfma_ms * 1e-3) / 1e12
-        out["mfma_roofline"] = {"bound": "mfma", "stages": "mlp + bwd_mlp + bwd_wgrad", "achieved": ach,
+        out["mfma_roofline"] = {"bound": "mfma", "stages": "mlp + bwd_mlp + bwd_wgrad",
+                                "flop_per_sample": flop / max(ne, 1), "achieved": ach,
                                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                                 "whole_step_frac": flop / (out["ms_per_step"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
     if sm.get("bwd_composite", 0.0) > 0:

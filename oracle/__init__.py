@@ -218,7 +218,10 @@ def render_rays(model, op, o, d, diagnostics=False):
     return rgb, dep, acc
 
 
-def render_pixels(model, op, cam, pix=None):
+def render_pixels(model, op, cam, pix=None, flip=False):
+    """diag['flip'] (with flip=True, for a model in bfloat16 mode): per pixel,
+    the largest colour change one bfloat16 rounding step of one MLP input
+    value could cause, weighted by its sample's compositing weight."""
     n = cam.width * cam.height if pix is None else len(pix)
     pix = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
     rgb = np.empty((n, 3), np.float64)
@@ -227,9 +230,13 @@ def render_pixels(model, op, cam, pix=None):
     ne = np.empty(n, np.int32)
     mg = np.empty(n, np.float64)
     am = np.empty(n, np.float64)
+    fl = np.empty(n, np.float64) if flip else None
     lib().orc_render_pixels(C.byref(model.grid), C.byref(model.mlp), C.byref(op), C.byref(cam),
-                            C.c_int64(n), _p(pix), _p(rgb), _p(dz), _p(acc), _p(ne), _p(mg), _p(am))
-    return rgb, dz, acc, {"n_eval": ne, "margin": mg, "acc_margin": am}
+                            C.c_int64(n), _p(pix), _p(rgb), _p(dz), _p(acc), _p(ne), _p(mg), _p(am), _p(fl))
+    diag = {"n_eval": ne, "margin": mg, "acc_margin": am}
+    if flip:
+        diag["flip"] = fl
+    return rgb, dz, acc, diag
 
 
 def warp(ref_cam, tgt_cam, T, ref_rgb, ref_depth, max_angle_deg=0.0):

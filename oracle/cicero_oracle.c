@@ -331,6 +331,57 @@ static void mlp_forward(const orc_mlp *m, const double *x, double *h1, double *h
     }
 }
 
+/* Size of one bfloat16 step at v (8 significant bits): the change of a
+ * rounded value when float32 and float64 arithmetic round it to adjacent
+ * bfloat16 values. */
+static double bf16_ulp(double v)
+{
+    double a = fabs(v);
+    if (a == 0.0) return 0.0;
+    int e;
+    frexp(a, &e);              /* a = mant * 2^e, mant in [0.5, 1) */
+    return ldexp(1.0, e - 8);
+}
+
+/* Largest change of the output colour (any channel) that one bfloat16
+ * rounding step of one MLP input value could cause at this sample, to first
+ * order: for a layer-l input v the output moves by c(1-c) |J[c][v]| ulp(v),
+ * where J is the derivative of the output logit with respect to v through
+ * the sample's active ReLUs and the (rounded) weights.  j1 [out][hidden] and
+ * j0 [out][in] are scratch.  Only meaningful with round_bf16. */
+static double bf16_flip_effect(const orc_mlp *m, const double *x, const double *h1, const double *h2,
+                               const double *c, double *j1, double *j0)
+{
+    int I = m->in_dim, H = m->hidden, O = m->out_dim;
+    for (int o = 0; o < O; ++o) {
+        for (int j = 0; j < H; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < H; ++k)
+                if (h2[k] > 0.0) s += wt(m, m->w2, (int64_t)o * H + k) * wt(m, m->w1, (int64_t)k * H + j);
+            j1[o * H + j] = s;
+        }
+        for (int i = 0; i < I; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < H; ++j)
+                if (h1[j] > 0.0) s += j1[o * H + j] * wt(m, m->w0, (int64_t)j * I + i);
+            j0[o * I + i] = s;
+        }
+    }
+    double worst = 0.0;
+    for (int o = 0; o < O && o < 3; ++o) {
+        double g = 0.0, e;
+        for (int k = 0; k < H; ++k)
+            if ((e = fabs(wt(m, m->w2, (int64_t)o * H + k)) * bf16_ulp(act(m, h2[k]))) > g) g = e;
+        for (int j = 0; j < H; ++j)
+            if ((e = fabs(j1[o * H + j]) * bf16_ulp(act(m, h1[j]))) > g) g = e;
+        for (int i = 0; i < I; ++i)
+            if ((e = fabs(j0[o * I + i]) * bf16_ulp(act(m, x[i]))) > g) g = e;
+        g *= c[o] * (1.0 - c[o]);
+        if (g > worst) worst = g;
+    }
+    return worst;
+}
+
 /* Per-sample record kept by the forward pass for the adjoint. */
 typedef struct {
     int k;
@@ -352,6 +403,7 @@ typedef struct {
     int32_t n_eval;  /* samples that went through the MLP */
     double margin;   /* min over termination decisions of |T/thr - 1| */
     uint64_t relu_sig;
+    double flip;     /* max over samples of w_k times bf16_flip_effect (when asked) */
 } ray_out;
 
 /* Render one ray (Sec. II-B; compositing as the standard quadrature).
@@ -359,11 +411,12 @@ typedef struct {
  * activations are stored for the adjoint. */
 static void render_ray(const orc_grid *g, const orc_mlp *m, const orc_opts *op,
                        const float o[3], const float d[3], ray_out *out,
-                       sample_rec *recs, double *xs, double *h1s, double *h2s, double *cs)
+                       sample_rec *recs, double *xs, double *h1s, double *h2s, double *cs, int want_flip)
 {
     int N = op->n_samples, C = g->n_feat;
     int I = m->in_dim, H = m->hidden, O = m->out_dim;
     double feat[64], x[256], h1[1024], h2[1024], c[8];
+    double j1[8 * 1024], j0[8 * 256];
     double wv[8];
     int64_t idx[8];
 
@@ -409,6 +462,10 @@ static void render_ray(const orc_grid *g, const orc_mlp *m, const orc_opts *op,
         }
         for (int ch = 0; ch < O && ch < 3; ++ch) out->rgb[ch] += w * c[ch];
         out->depth_t += w * (double)tk;
+        if (want_flip) {
+            double fe = w * bf16_flip_effect(m, x, h1, h2, c, j1, j0);
+            if (fe > out->flip) out->flip = fe;
+        }
         if (recs) {
             int n = out->n_eval;
             sample_rec *r = &recs[n];
@@ -554,7 +611,7 @@ void orc_render_rays(const orc_grid *g, const orc_mlp *m, const orc_opts *op, in
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < n; ++r) {
         ray_out ro;
-        render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, NULL, NULL, NULL, NULL, NULL);
+        render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, NULL, NULL, NULL, NULL, NULL, 0);
         for (int ch = 0; ch < 3; ++ch) rgb[3 * r + ch] = ro.rgb[ch];
         depth_t[r] = ro.depth_t;
         acc[r] = ro.acc;
@@ -577,7 +634,7 @@ static double frame_depth(const orc_camera *cam, const float d[3], double depth_
  * acc [n]; acc_margin[n] = |acc/void_acc - 1| (may be NULL). */
 void orc_render_pixels(const orc_grid *g, const orc_mlp *m, const orc_opts *op, const orc_camera *cam,
                        int64_t n, const int64_t *pix, double *rgb, double *depth_z, double *acc,
-                       int32_t *n_eval, double *margin, double *acc_margin)
+                       int32_t *n_eval, double *margin, double *acc_margin, double *flip)
 {
     int64_t total = pix ? n : (int64_t)cam->width * cam->height;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -586,13 +643,14 @@ void orc_render_pixels(const orc_grid *g, const orc_mlp *m, const orc_opts *op, 
         float o[3], d[3];
         pixel_ray_f32(cam, (int)(p % cam->width), (int)(p / cam->width), o, d);
         ray_out ro;
-        render_ray(g, m, op, o, d, &ro, NULL, NULL, NULL, NULL, NULL);
+        render_ray(g, m, op, o, d, &ro, NULL, NULL, NULL, NULL, NULL, flip != NULL);
         for (int ch = 0; ch < 3; ++ch) rgb[3 * r + ch] = ro.rgb[ch];
         depth_z[r] = frame_depth(cam, d, ro.depth_t, ro.acc, op->void_acc);
         acc[r] = ro.acc;
         if (n_eval) n_eval[r] = ro.n_eval;
         if (margin) margin[r] = ro.margin;
         if (acc_margin) acc_margin[r] = fabs(ro.acc / (double)op->void_acc - 1.0);
+        if (flip) flip[r] = ro.flip;
     }
 }
 
@@ -756,7 +814,7 @@ void orc_sparw(const orc_grid *g, const orc_mlp *m, const orc_opts *op,
     double *hr = (double *)malloc(sizeof(double) * 3 * (nh > 0 ? nh : 1));
     double *hd = (double *)malloc(sizeof(double) * (nh > 0 ? nh : 1));
     double *ha = (double *)malloc(sizeof(double) * (nh > 0 ? nh : 1));
-    if (nh > 0) orc_render_pixels(g, m, op, tgt, nh, holes, hr, hd, ha, NULL, NULL, NULL);
+    if (nh > 0) orc_render_pixels(g, m, op, tgt, nh, holes, hr, hd, ha, NULL, NULL, NULL, NULL);
     for (int64_t p = 0; p < np; ++p) {
         for (int ch = 0; ch < 3; ++ch) out_rgb[3 * p + ch] = wr[3 * p + ch];
         out_depth[p] = wd[p];
@@ -813,7 +871,7 @@ void orc_render_backward(const orc_grid *g, const orc_mlp *m, const orc_opts *op
 #pragma omp for schedule(dynamic, 4)
         for (int64_t r = 0; r < n; ++r) {
             ray_out ro;
-            render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, recs, xs, h1s, h2s, cs);
+            render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, recs, xs, h1s, h2s, cs, 0);
             if (rgb_out) for (int ch = 0; ch < 3; ++ch) rgb_out[3 * r + ch] = ro.rgb[ch];
             if (depth_out) depth_out[r] = ro.depth_t;
             if (acc_out) acc_out[r] = ro.acc;

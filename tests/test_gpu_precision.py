@@ -3,6 +3,7 @@ weights, FP32 accumulation).  The kernel is checked tightly against the
 oracle in its BF16-rounding mode, and its error against the float64 oracle
 is stated next to the FP32 path's."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -21,65 +22,101 @@ def _psnr(a, b):
 
 
 def test_bf16_kernel_matches_bf16_oracle():
-    """Same rounding rule on both sides: remaining differences come from
-    float32 vs float64 accumulation, plus rare inputs that sit next to a
-    bfloat16 rounding boundary and round differently."""
+    """Same rounding rule on both sides: the GPU accumulates in float32 where
+    the oracle uses float64, so a value that sits closer to a bfloat16
+    rounding boundary than that difference can round to the adjacent
+    bfloat16 number on one side.  Bound per pixel: 2e-5 for the float32
+    accumulation (twice the FP32 path's 1e-5: the BF16 kernel also runs the
+    output layer on the matrix unit) plus the oracle's one-step bound, the
+    largest colour change one bfloat16 step of one MLP input value can make
+    in that pixel (its Jacobian through the active ReLUs times the step,
+    times the sample's weight).  99.5% of pixels stay within 2e-5."""
     import paper_2404_11852_amd as cic
     print_case("bf16 kernel vs bf16-rounding oracle, 64x64")
     dens, feats = synth.make_scene(32, seed=0)
     mlp = synth.make_mlp(1, bias_std=0.1)
     gm = cic.Model(dens, feats, mlp, device="cuda", density_shift=synth.DENSITY_SHIFT, compute=cic.CIC_BF16)
     om = oracle.Model(dens, feats, mlp, density_shift=synth.DENSITY_SHIFT, round_bf16=True)
+    gc, oc = cams(64, 64, synth.orbit_pose(0))
+    orgb, _, _, diag = oracle.render_pixels(om, oracle.opts(64), oc, flip=True)
+    flip = diag["flip"]
     for order in (0, 1):
-        gc, oc = cams(64, 64, synth.orbit_pose(0))
         rgb, _, _ = cic.render_frame(gm, cic.make_opts(64, order=order), gc)
-        orgb, _, _, _ = oracle.render_pixels(om, oracle.opts(64), oc)
         err = np.abs(to_np(rgb) - orgb).max(axis=1)
-        print("order %d: median %.2e, 99.5%% %.2e, max %.2e" % (order, np.median(err), np.quantile(err, 0.995),
-                                                               err.max()))
+        ratio = (err - 2e-5) / np.maximum(flip, 1e-300)
+        print("order %d: median %.2e, 99.5%% %.2e, max %.2e; one-step bound median %.2e max %.2e; "
+              "worst (err - 2e-5) / bound %.3f" % (order, np.median(err), np.quantile(err, 0.995), err.max(),
+                                                    np.median(flip), flip.max(), ratio.max()))
         assert np.quantile(err, 0.995) <= 2e-5
-        assert err.max() <= 2e-3
+        assert np.all(err <= 2e-5 + flip), np.argmax(err - flip)
+
+
+_GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "amb17_reference.npz")
 
 
 def test_precision_path_eight_views_one_launch():
     """8 views of 800x800 (all 5.12M rays in one render_rays call), FP16
-    grids, BF16 MLP; 4096 seeded pixels compared with the float64 oracle,
-    next to the FP32 path on the same views.  The BF16 path must stay within
-    0.1 dB of the float64 oracle's own PSNR against a converged reference
-    (1024 samples, no skipping or termination) on those pixels."""
+    grids, BF16 MLP, on 16,384 seeded pixels per view (131,072) against the
+    float64 oracle's stored colours (tests/golden/amb17_reference.npz,
+    written by make_amb17_reference.py from the oracle alone; a seeded
+    subset is recomputed here and must match).  The BF16 path must stay
+    within 0.1 dB of the oracle's own PSNR against the converged reference
+    G (1024 samples, no skipping or termination).  The two error sources
+    are measured apart: FP16 grid with the FP32 MLP, FP32 grid with the
+    BF16 MLP."""
     import paper_2404_11852_amd as cic
-    print_case("precision path 8 x 800x800")
+    print_case("precision path 8 x 800x800, 131072 pixels")
+    gold = np.load(_GOLD)
+    pix, o64, gref = gold["pix"], gold["o64"].astype(np.float64), gold["g"].astype(np.float64)
+    V, P = pix.shape
     W = H = 800
     dens, feats = synth.make_scene(160, seed=0)
     mlp = synth.make_mlp(1)
-    g16 = cic.Model(dens, feats, mlp, device="cuda", storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
-                    compute=cic.CIC_BF16)
-    g32 = cic.Model(dens, feats, mlp, device="cuda", density_shift=synth.DENSITY_SHIFT)
-    occ = g32.build_occupancy(synth.OCC_SIGMA)
-    g16.set_occupancy(occ)
-    poses = synth.sphere_poses(8, seed=2)
+    om = oracle.Model(dens, feats, mlp, density_shift=synth.DENSITY_SHIFT)
+    om.set_occupancy(oracle.build_occupancy(om, synth.OCC_SIGMA))
+    poses = synth.sphere_poses(V, seed=2)
     f, cx, cy = synth.intrinsics(W, H)
+    # the stored values are the oracle's: recompute a seeded subset
+    chk = np.sort(np.random.default_rng(5).choice(V * P, 192, replace=False))
+    oo, dd = [], []
+    for k in chk:
+        v, q = divmod(int(k), P)
+        a, b = oracle.generate_rays(oracle.camera(W, H, f, cx, cy, synth.as_f32(poses[v])),
+                                    np.array([pix[v, q]], np.int64))
+        oo.append(a)
+        dd.append(b)
+    oo, dd = np.concatenate(oo), np.concatenate(dd)
+    r1, _, _ = oracle.render_rays(om, oracle.opts(256, 1e-4, True), oo, dd)
+    r2, _, _ = oracle.render_rays(om, oracle.opts(1024), oo, dd)
+    assert np.array_equal(r1.astype(np.float32), gold["o64"][chk])
+    assert np.array_equal(r2.astype(np.float32), gold["g"][chk])
+
+    models = {}
+    for name, storage, compute in (("f16_bf16", torch.float16, cic.CIC_BF16), ("f32_bf16", torch.float32, cic.CIC_BF16),
+                                   ("f16_f32", torch.float16, cic.CIC_F32), ("f32_f32", torch.float32, cic.CIC_F32)):
+        models[name] = cic.Model(dens, feats, mlp, device="cuda", storage=storage,
+                                 density_shift=synth.DENSITY_SHIFT, compute=compute)
+    occ = models["f32_f32"].build_occupancy(synth.OCC_SIGMA)
+    assert np.array_equal(om.occ, to_np(occ))
+    for m in models.values():
+        m.set_occupancy(occ)
     rays = [cic.generate_rays(cic.make_camera(W, H, f, cx, cy, synth.as_f32(p))) for p in poses]
     o = torch.cat([r[0] for r in rays])
     d = torch.cat([r[1] for r in rays])
+    sel = torch.from_numpy((np.arange(V)[:, None] * (W * H) + pix).reshape(-1).astype(np.int64)).cuda()
     go = cic.make_opts(256, 1e-4, True)
-    n16 = torch.zeros(1, dtype=torch.int64, device="cuda")
-    rgb16, _, _ = cic.render_rays(g16, go, o, d, n_eval=n16)
-    rgb32, _, _ = cic.render_rays(g32, go, o, d)
-    torch.cuda.synchronize()
-    om = oracle.Model(dens, feats, mlp, density_shift=synth.DENSITY_SHIFT)
-    om.set_occupancy(oracle.build_occupancy(om, synth.OCC_SIGMA))
-    assert np.array_equal(om.occ, to_np(occ))
-    rng = np.random.default_rng(17)
-    sel = np.sort(rng.choice(8 * W * H, 4096, replace=False))
-    os_, ds_ = to_np(o)[sel], to_np(d)[sel]
-    o64, _, _ = oracle.render_rays(om, oracle.opts(256, 1e-4, True), os_, ds_)
-    gref, _, _ = oracle.render_rays(om, oracle.opts(1024), os_, ds_)
-    b16, f32 = to_np(rgb16)[sel], to_np(rgb32)[sel]
-    res = {"max_abs_bf16": float(np.abs(b16 - o64).max()), "max_abs_fp32": float(np.abs(f32 - o64).max()),
-           "psnr_o64_bf16": _psnr(o64, b16), "psnr_o64_fp32": _psnr(o64, f32),
-           "psnr_G_o64": _psnr(gref, o64), "psnr_G_bf16": _psnr(gref, b16)}
+    out = {}
+    for name, m in models.items():
+        n_eval = torch.zeros(1, dtype=torch.int64, device="cuda")
+        rgb, _, _ = cic.render_rays(m, go, o, d, n_eval=n_eval)
+        out[name] = to_np(rgb[sel]).astype(np.float64)
+        assert int(n_eval.item()) > 0
+    res = {"psnr_G_o64": _psnr(gref, o64)}
+    for name, v in out.items():
+        res["psnr_G_" + name] = _psnr(gref, v)
+        res["psnr_o64_" + name] = _psnr(o64, v)
+        res["max_abs_o64_" + name] = float(np.abs(v - o64).max())
+    res["margin_db"] = res["psnr_G_f16_bf16"] - (res["psnr_G_o64"] - 0.1)
     print(res)
-    assert res["psnr_G_bf16"] >= res["psnr_G_o64"] - 0.1
-    assert res["max_abs_fp32"] <= 3e-4   # termination flips included (float32 path)
-    assert int(n16.item()) > 0
+    assert res["margin_db"] >= 0.0
+    assert res["max_abs_o64_f32_f32"] <= 3e-4   # termination flips included (float32 path)
