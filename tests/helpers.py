@@ -71,3 +71,33 @@ def compare(got, want, margin=None, tol=TOL, flip_tol=FLIP_TOL, what="rgb"):
     if flagged.any():
         assert float(err[flagged].max()) <= flip_tol, "%s: flagged rows error %.3g" % (what, err[flagged].max())
     return worst, int(flagged.sum())
+
+
+def check_sparw_frame(rgb, dz, mask, orc_model, oop, ref_ocam, ref_rgb32, ref_dz32, tgt_ocam, T, max_angle=0.0,
+                      sample=None, seed=0):
+    """Element-wise parity of one SpaRW target frame (GPU arrays rgb [P][3],
+    z-depth [P], mask [P]) against the oracle driven by the same float32
+    reference frame and transform: the hole mask, and the colour and depth
+    of every warped pixel, are bit-exact; re-rendered (hole) pixels meet the
+    render tolerance (flip band apart), all of them or a seeded sample of
+    `sample`.  Returns (holes, holes checked)."""
+    wr, wd, wm, _ = oracle.warp(ref_ocam, tgt_ocam, T, ref_rgb32, ref_dz32, max_angle)
+    assert np.array_equal(mask, wm), "mask differs at %d pixels" % int((mask != wm).sum())
+    keep = wm == 0
+    assert np.array_equal(rgb[keep], wr[keep]), "warped colour"
+    assert np.array_equal(np.nan_to_num(dz[keep], posinf=-1.0), np.nan_to_num(wd[keep], posinf=-1.0)), "warped depth"
+    holes = np.nonzero(wm)[0]
+    chk = holes
+    if sample is not None and holes.size > sample:
+        chk = np.sort(np.random.default_rng(seed).choice(holes, sample, replace=False))
+    if chk.size:
+        orgb, odz, oacc, diag = oracle.render_pixels(orc_model, oop, tgt_ocam, chk)
+        compare(rgb[chk], orgb, margin=diag["margin"])
+        am = diag["acc_margin"]
+        sure = am > 1e-3
+        assert np.array_equal(np.isinf(dz[chk])[sure], np.isinf(odz)[sure]), "void decision"
+        fin = sure & np.isfinite(odz)
+        if fin.any():
+            derr = np.abs(dz[chk][fin] - odz[fin]) * oacc[fin] / (1 + np.abs(odz[fin]))
+            assert derr.max() < 2e-5, derr.max()
+    return int(holes.size), int(chk.size)

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import synth
-from helpers import Pair, cams, compare, print_case, to_np
+from helpers import Pair, cams, check_sparw_frame, compare, print_case, to_np
 from oracle import sequence as seq
 
 pytestmark = pytest.mark.gpu
@@ -82,9 +82,12 @@ def test_temporal_equals_chained_single_calls(n, window):
 
 
 def test_temporal_matches_oracle():
-    """Chained warps: a pixel decided differently (float32 GPU frame vs
-    float64 oracle frame at a pixel edge) is carried into the next frames, so
-    agreement is held per frame on nearly every pixel plus a PSNR floor."""
+    """Temp-N element by element: full-render frames against the oracle's
+    renders (render tolerance, flip band apart); every warped frame against
+    the oracle's warp and sparse render driven by the GPU's own previous
+    output frame and the library's transform, so the hole mask and every
+    warped pixel are bit-exact and the re-rendered pixels meet the render
+    tolerance."""
     import paper_2404_11852_amd as cic
     print_case("Temp-4 vs oracle 64x64 n=9")
     W = H = 64
@@ -94,16 +97,17 @@ def test_temporal_matches_oracle():
     opts = cic.make_opts(256, 1e-4, True)
     rgb, dz, mask, nm = cic.render_temporal(p.gpu, opts, gcams, window)
     f, cx, cy = synth.intrinsics(W, H)
-    ofr = seq.render_temporal(p.orc, oracle.opts(256, 1e-4, True), W, H, f, cx, cy, poses, window)
-    g_rgb, g_mask = to_np(rgb), to_np(mask)
+    oop = oracle.opts(256, 1e-4, True)
+    g_rgb, g_dz, g_mask = to_np(rgb), to_np(dz), to_np(mask)
+    ocams = [oracle.camera(W, H, f, cx, cy, q.reshape(12)) for q in poses]
     for k in range(n):
-        orgb, _, omask, onm = ofr[k]
-        mism = int((g_mask[k] != omask).sum())
-        err = np.abs(g_rgb[k].astype(np.float64) - orgb).max(axis=1)
-        close = float((err <= 1e-4).mean())
-        mse = float(((g_rgb[k].astype(np.float64) - orgb) ** 2).mean())
-        psnr = 10 * np.log10(1.0 / max(mse, 1e-30))
-        print("frame %d: mask mismatches %d, rendered gpu %d oracle %d, within 1e-4: %.5f, PSNR %.1f dB"
-              % (k, mism, int(nm[k]), onm, close, psnr), flush=True)
-        assert mism <= max(2, int(0.004 * W * H)), k
-        assert close >= 0.99 and psnr >= 45.0, k
+        if k % window == 0:
+            orgb, _, _, diag = oracle.render_pixels(p.orc, oop, ocams[k])
+            compare(g_rgb[k], orgb, margin=diag["margin"])
+            assert int(nm[k]) == W * H
+            continue
+        T = np.array(cic.relative_pose(poses[k - 1], poses[k]), np.float32)
+        holes, _ = check_sparw_frame(g_rgb[k], g_dz[k], g_mask[k], p.orc, oop, ocams[k - 1], g_rgb[k - 1],
+                                     g_dz[k - 1], ocams[k], T)
+        assert holes == int(nm[k]), k
+        print("frame %d: %d holes, mask and warped pixels bit-exact" % (k, holes), flush=True)
