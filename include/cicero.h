@@ -213,6 +213,23 @@ int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_t
                float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
                void *ws, size_t ws_bytes, cic_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * warp as warp_frame, with the same arguments and results (bit for bit),
+ * but without a workspace.  Its z-buffer is a device array inside the
+ * library, one per GPU, of 2^21 64-bit entries (16 MiB, held until the
+ * process ends), so the target frame has at most 2,097,152 pixels; larger
+ * targets return CIC_ERR_INVALID before anything is launched.  The call
+ * allocates nothing (no hipMalloc, no library allocation); its first call
+ * on a device looks up that device's array.  Every call on one GPU uses the
+ * same array: calls that overlap on one GPU (different streams, or several
+ * host threads) race and give undefined results; calls ordered on one
+ * stream are safe, each fills the z-buffer before using it. */
+int warp_frame_noalloc(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12],
+                       const float *ref_rgb, const float *ref_depth_z, float max_angle_deg,
+                       float *tgt_rgb, float *tgt_depth_z, uint8_t *mask, int32_t *src_index,
+                       cic_stream_t stream);
+
 /* SpaRW for one target frame (Sec. III-B, Eq. 4): warp_frame, then render the
  * pixels of the mask (void pixels, those reached only by directions, are not
  * re-rendered) with render_rays and put them in place of the warped values.

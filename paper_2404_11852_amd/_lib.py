@@ -57,7 +57,7 @@ class Camera(C.Structure):
 EXPORTS = ["cic_workspace_bytes", "cic_last_error_message", "build_occupancy", "generate_rays", "render_rays",
            "render_frame", "warp_frame", "render_frame_sparw", "render_backward", "cic_timing_enable",
            "cic_timing_read", "cic_extrapolate_pose", "cic_relative_pose", "render_sequence", "cic_timing_frames",
-           "render_frame_ds", "cic_stream_create_cu_masked", "cic_stream_destroy"]
+           "render_frame_ds", "cic_stream_create_cu_masked", "cic_stream_destroy", "warp_frame_noalloc"]
 STAGES = ["march", "compact", "mlp", "reduce", "warp", "raygen", "bwd_composite", "bwd_mlp", "bwd_wgrad", "embed"]
 
 _lib = None
@@ -94,6 +94,7 @@ def lib():
                                               vp, vp, vp, vp, vp, vp, u64, vp, vp]
                 L.cic_stream_create_cu_masked.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
                 L.cic_stream_destroy.argtypes = [vp]
+                L.warp_frame_noalloc.argtypes = [vp, vp, vp, vp, vp, f, vp, vp, vp, vp, vp]
                 L.cic_timing_frames.argtypes = [vp, C.c_int]
                 L.render_frame_ds.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, u64, vp]
                 for name in EXPORTS[2:]:
@@ -249,6 +250,15 @@ def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask
     _check(lib().warp_frame(C.byref(ref_cam), C.byref(tgt_cam), Tc, _ptr(ref_rgb), _ptr(ref_depth),
                             C.c_float(max_angle_deg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(src_index),
                             _ptr(ws), C.c_size_t(ws.numel()), _stream()))
+
+
+def warp_frame_noalloc(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask, src_index=None,
+                       max_angle_deg=0.0):
+    """warp_frame without a workspace (the library's own z-buffer array)."""
+    Tc = (C.c_float * 12)(*[float(v) for v in torch.as_tensor(T, dtype=torch.float32).reshape(12).tolist()])
+    _check(lib().warp_frame_noalloc(C.byref(ref_cam), C.byref(tgt_cam), Tc, _ptr(ref_rgb), _ptr(ref_depth),
+                                    C.c_float(max_angle_deg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask),
+                                    _ptr(src_index), _stream()))
 
 
 def render_frame_sparw(grid, mlp, opts, ref_cam, ref_rgb, ref_depth, tgt_cam, T, out_rgb, out_depth, mask,

@@ -13,6 +13,14 @@
 
 using namespace cic;
 
+// Z-buffer of warp_frame_noalloc, for callers that cannot allocate device
+// memory: one 64-bit key per target pixel, at most kNoAllocPixels target
+// pixels (16 MiB per GPU, held until the process ends).  Host code never
+// uses this name as an address: each device's copy is reached through the
+// pointer hipGetSymbolAddress returns for it (noalloc_zbuf below).
+constexpr int64_t kNoAllocPixels = (int64_t)1 << 21;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocPixels];
+
 namespace {
 
 thread_local std::string g_err;
@@ -577,6 +585,32 @@ int check_warp_args(const cic_camera *ref, const cic_camera *tgt, const float re
     return CIC_OK;
 }
 
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+int noalloc_zbuf(uint64_t **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return fail(CIC_ERR_HIP, "no HIP device");
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(CIC_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint64_t *)g_scratch_ptr[dev];
+    return CIC_OK;
+}
+
 void frame_mark(hipStream_t s)
 {
     if (!g_timing.on) return;
@@ -715,6 +749,27 @@ int warp_frame(const cic_camera *ref, const cic_camera *tgt, const float ref_T_t
                     tgt_depth_z, mask, src_index, nullptr, nullptr, (hipStream_t)stream);
     }
     return after_launch("warp_frame");
+}
+
+int warp_frame_noalloc(const cic_camera *ref, const cic_camera *tgt, const float ref_T_tgt[12], const float *ref_rgb,
+                       const float *ref_depth_z, float max_angle_deg, float *tgt_rgb, float *tgt_depth_z,
+                       uint8_t *mask, int32_t *src_index, cic_stream_t stream)
+{
+    int rc;
+    if ((rc = check_warp_args(ref, tgt, ref_T_tgt, ref_rgb, ref_depth_z, max_angle_deg, tgt_rgb, tgt_depth_z, mask)))
+        return rc;
+    const int64_t np = (int64_t)tgt->width * tgt->height;
+    if (np > kNoAllocPixels)
+        return fail(CIC_ERR_INVALID, "target frame has %lld pixels; warp_frame_noalloc handles at most %lld",
+                    (long long)np, (long long)kNoAllocPixels);
+    if ((rc = check_device())) return rc;
+    uint64_t *zbuf = nullptr;
+    if ((rc = noalloc_zbuf(&zbuf))) return rc;
+    // the warp's first kernel fills the z-buffer with the empty key, so no
+    // earlier call's contents are read
+    launch_warp(*ref, *tgt, ref_T_tgt, cos_limit(max_angle_deg), ref_rgb, ref_depth_z, zbuf, tgt_rgb, tgt_depth_z,
+                mask, src_index, nullptr, nullptr, (hipStream_t)stream);
+    return after_launch("warp_frame_noalloc");
 }
 
 int render_frame_sparw(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, const cic_camera *ref,
