@@ -215,6 +215,7 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
         b.perm = cv.take<uint32_t>(ns);
         b.work_ctr = cv.take<uint32_t>(kXcds);
         b.seg_off = cv.take<uint32_t>(n_bricks + 1);
+        b.seg_brick = cv.take<uint32_t>(tile_max_segments(n_bricks, ns));
     }
     b.n_bricks = n_bricks;
     return b;
@@ -272,11 +273,8 @@ void carve_backward(Carver &cv, int64_t nc, int N, RenderBufs &b, BackwardBufs &
     const int64_t ns = nc * (int64_t)N;
     b.slot_t = cv.take<float>(ns);
     b.rec_t = cv.take<float>(ns);
-    b.stage = cv.take<float>(ns * kStageStride);
-    b.stage_mask = cv.take<uint32_t>(ns * 8);
-    bb.rec_dc = cv.take<float>(3 * ns);
     bb.partials = cv.take<float>((int64_t)kWgBlocks * kPartialFloats);
-    bb.df_sorted = cv.take<float>(12 * ns);
+    bb.rec_df = cv.take<float>(12 * ns);
     bb.rec_draw = cv.take<float>(ns);
     bb.seg_tiles = cv.take<float>(fg_max_segments(b.n_bricks, ns) * kFgTileFloats);
 }
@@ -1055,21 +1053,15 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
             }
         }
         {
-            StageTimer t(CIC_STAGE_MLP, s);
-            launch_mlp_forward_staged(gk, *mlp, b, true, s);
+            // recomputed forward (its colours go to the compositing adjoint),
+            // MLP backward and weight gradients
+            StageTimer t(CIC_STAGE_BWD_MLP, s);
+            launch_mlp_adjoint(gk, *mlp, b, bb, s);
         }
         {
             StageTimer t(CIC_STAGE_BACKWARD, s);
             launch_backward_composite(gk, ok_, b, bb, s);
-        }
-        {
-            StageTimer t(CIC_STAGE_BWD_MLP, s);
-            launch_mlp_backward(gk, *mlp, b, bb, s);
             launch_feature_grads_bricks(gk, b, bb, s);
-        }
-        {
-            StageTimer t(CIC_STAGE_BWD_WGRAD, s);
-            launch_weight_grads(*mlp, b, bb, s);
         }
     }
     return after_launch("render_backward");

@@ -32,9 +32,6 @@ struct RenderBufs {
     float *rec_c;          // [n*N*3] MLP colour per live sample
     float *slot_t;         // [n*N] transmittance T_k of live samples (adjoint only; nullable)
     float *rec_t;          // [n*N] compacted T_k (adjoint only; nullable)
-    float *stage;          // [n*N][kStageStride] per-sample MLP vectors (adjoint only; nullable)
-    uint32_t *stage_mask;  // [n*N][8] ReLU masks of the staged h1 (words 0-3) and h2 (words 4-7): word q, bit
-                           // 4t + r is row 16t + 4q + r > 0 (adjoint only)
     float *z0;             // [n][128] per-ray direction term of layer 0 (FP32 compute)
     uint32_t *enc;         // [n][16] per-ray view encoding in BF16: lane group q's 7 inputs in words 4q..4q+3
     // voxel order
@@ -42,6 +39,7 @@ struct RenderBufs {
     uint32_t *brick_off;   // [n_bricks+1] counts, then cursors
     uint32_t *brick_tmp;   // block sums for the brick scan
     uint32_t *perm;        // [n*N] sample order for the MLP stage
+    uint32_t *seg_brick;   // voxel order (nullable): [max segments] brick of each segment of the LDS-tile kernels
     int64_t n_bricks;
     uint32_t *work_ctr;    // voxel order: per-XCD segment counters of the LDS-tile MLP kernels (kXcds words)
     uint32_t *seg_off;     // voxel order: [n_bricks+1] exclusive scan of segments per brick
@@ -49,16 +47,12 @@ struct RenderBufs {
                            // persistent kernels' grids
 };
 
-// Per-sample row of MLP vectors kept for the weight gradients (adjoint):
-// inputs with a constant 1 in the padding slot (so the bias gradient falls
-// out of the same product), both hidden activations, the first hidden
-// layer's pre-activation gradient and the output-logit gradient.  The second
-// layer's pre-activation gradient, dp1 = [h2 > 0] (W2^T dlogit), is not
-// stored: the weight-gradient kernel recomputes it from the row into its LDS
-// copy, at kStDP1 just past the stored part.
-constexpr int kStX = 0, kStH1 = 40, kStH2 = 168, kStDP0 = 296, kStDL = 424;
-constexpr int kStageStride = 440;   // stored row; the logit-gradient block is 16 wide (3 used, rest zero)
-constexpr int kStDP1 = kStageStride;   // LDS copy only (128 floats)
+// Per-sample row of MLP vectors the adjoint's weight gradients read from LDS:
+// inputs with a constant 1 in the padding slot (so the bias gradients fall
+// out of the same products), both hidden activations, the first hidden
+// layer's pre-activation gradient, the output-logit gradient (16 wide, 3
+// used) and the second hidden layer's pre-activation gradient.
+constexpr int kStX = 0, kStH1 = 40, kStH2 = 168, kStDP0 = 296, kStDL = 424, kStDP1 = 440;
 
 // scan.hip
 size_t scan_tmp_elems(int64_t n);
@@ -76,10 +70,15 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 // segments of at most kTileSeg samples per brick for the LDS-tile MLP kernels,
 // and of at most kFgSeg samples for the brick-tile gradient accumulation
 constexpr int kTileSeg = 2048;
+__host__ __device__ inline int64_t tile_max_segments(int64_t n_bricks, int64_t ns)
+{
+    return n_bricks + ns / kTileSeg + 1;
+}
 constexpr int kFgSeg = 512;
 // seg_off[k] = first segment of brick k (exclusive scan of ceil(count / seg));
-// seg_off[n_bricks] = the number of segments
-void launch_brick_segments(const RenderBufs &b, int seg, hipStream_t s);
+// seg_off[n_bricks] = the number of segments; with `table` (seg ==
+// kTileSeg), also seg_brick, the brick of every segment
+void launch_brick_segments(const RenderBufs &b, int seg, bool table, hipStream_t s);
 
 // upsample.hip
 void launch_upsample_bilinear(const float *lo, int w, int h, float *out, int W, int H, int s, hipStream_t st);
@@ -103,8 +102,6 @@ void launch_mlp_forward_bf16(const GridK &g, const cic_mlp &m, const RenderBufs 
 void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s);
 // per-ray direction term of layer 0 into b.z0 (rays with live samples)
 void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s);
-// forward with per-sample staging of x, h1, h2 (float32 grids, ray order)
-void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s);
 
 // warp.hip
 void launch_warp(const cic_camera &ref, const cic_camera &tgt, const float T[12], float cmin, const float *ref_rgb,
@@ -117,9 +114,8 @@ struct BackwardBufs {
     const float *d_rgb, *d_depth_t, *d_acc;
     float *d_density, *d_features;
     float *d_w0, *d_b0, *d_w1, *d_b1, *d_w2, *d_b2;
-    float *rec_dc;         // [n*N*3] dL/dc per live sample
-    float *partials;       // weight-gradient partial sums, kWgBlocks * kPartialFloats
-    float *df_sorted;      // [n*N][12] feature gradient per sample in brick order
+    float *partials;       // weight-gradient partial sums, one per adjoint workgroup (at most kWgBlocks)
+    float *rec_df;         // [n*N][12] feature gradient per live sample (ray order)
     float *rec_draw;       // [n*N] raw-density gradient per live sample
     float *seg_tiles;      // [max segments][kFgTileFloats] each segment's accumulated gradient tile
 };
@@ -131,8 +127,9 @@ constexpr int kWgBlocks = 1024;
 constexpr int kPartialFloats = 128 * 48 + 128 * 128 + 16 * 128 + 128 * 16 + 16 * 16;
 void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs &b, const BackwardBufs &bb,
                                hipStream_t s);
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
-void launch_weight_grads(const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
+// recomputed forward, MLP backward and weight gradients, fused (ray order);
+// also writes the samples' colours rec_c, which the compositing adjoint reads
+void launch_mlp_adjoint(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);
 // brick-tile accumulation of the feature and density gradients written by the
 // MLP backward and the compositing adjoint, then their addition to the grids
 void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s);

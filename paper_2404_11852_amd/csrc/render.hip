@@ -347,12 +347,22 @@ __global__ void k_brick_segments(RenderBufs b, uint32_t seg)
     b.seg_off[k] = (end - start + seg - 1u) / seg;
 }
 
-void launch_brick_segments(const RenderBufs &b, int seg, hipStream_t s)
+// Brick of every segment: brick k writes its own segments' entries.
+__global__ void k_segment_bricks(RenderBufs b)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n_bricks) return;
+    for (uint32_t q = b.seg_off[k]; q < b.seg_off[k + 1]; ++q) b.seg_brick[q] = (uint32_t)k;
+}
+
+void launch_brick_segments(const RenderBufs &b, int seg, bool table, hipStream_t s)
 {
     if (b.n_bricks > 0)
         hipLaunchKernelGGL(k_brick_segments, dim3((unsigned)((b.n_bricks + 255) / 256)), dim3(256), 0, s, b,
                            (uint32_t)seg);
     launch_exclusive_scan(b.seg_off, b.seg_off, b.brick_tmp, b.n_bricks, s);   // also writes the total
+    if (table && b.seg_brick && seg == kTileSeg && b.n_bricks > 0)
+        hipLaunchKernelGGL(k_segment_bricks, dim3((unsigned)((b.n_bricks + 255) / 256)), dim3(256), 0, s, b);
 }
 
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
