@@ -332,8 +332,9 @@ int render_frame_ds(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
                     int32_t factor, float *rgb, int64_t *n_eval, void *ws, size_t ws_bytes, cic_stream_t stream);
 
 /* Adjoint of render_rays (the derivative of the same quadrature; the paper
- * itself is inference-only).  The forward is recomputed per ray; nothing
- * from a previous forward call is needed.  Upstream gradients d_rgb [n][3],
+ * itself is inference-only).  The forward is recomputed per ray, on chip,
+ * inside the fused MLP adjoint kernel (no per-sample activations go to
+ * memory); nothing from a previous forward call is needed.  Upstream gradients d_rgb [n][3],
  * d_depth_t [n] (nullable), d_acc [n] (nullable).  Accumulates (+=) into
  * d_density [res0][res1][res2], d_features [res0][res1][res2][12] and the
  * MLP gradients shaped like the weights (all float32, device).  float32
@@ -363,9 +364,9 @@ enum {
     CIC_STAGE_REDUCE = 3,     /* per-ray accumulation */
     CIC_STAGE_WARP = 4,       /* z-buffer splat + resolve */
     CIC_STAGE_RAYGEN = 5,     /* pixel rays */
-    CIC_STAGE_BACKWARD = 6,   /* adjoint: compositing adjoint + density scatter */
-    CIC_STAGE_BWD_MLP = 7,    /* adjoint: MLP backward + feature scatter */
-    CIC_STAGE_BWD_WGRAD = 8,  /* adjoint: weight-gradient products */
+    CIC_STAGE_BACKWARD = 6,   /* adjoint: compositing adjoint + grid-gradient tiles (feature and density) */
+    CIC_STAGE_BWD_MLP = 7,    /* adjoint: recomputed forward + MLP backward + weight gradients (fused) */
+    CIC_STAGE_BWD_WGRAD = 8,  /* no launches (the weight gradients are part of CIC_STAGE_BWD_MLP) */
     CIC_STAGE_EMBED = 9,      /* per-ray direction term of layer 0 */
     CIC_STAGE_COUNT = 10
 };

@@ -8,23 +8,23 @@
 // expected distance gives delta (T_{k+1} t_k - D_k) with D_k = sum_{j>k} w_j t_j,
 // and the opacity 1 - T_stop gives delta T_stop.  dC/dc_k = w_k.
 //
-// Kernels (one backward pass over a chunk of rays, samples in brick order;
-// the forward has already been recomputed into the workspace, with
-// per-sample MLP vectors and ReLU sign masks staged):
+// Kernels (one backward pass over a chunk of rays, after the march and the
+// bucketing):
+//  - k_mlp_adjoint: per 16-sample batch (ray order), the forward recomputed
+//    on chip (its colours c_k kept for the next kernel), the MLP backward
+//    from dL/dc_k = w_k dL/dC on FP32 MFMA (the 12 feature gradients written
+//    per sample) and the weight-gradient outer products accumulated per
+//    workgroup; k_wgrad_apply adds the workgroups' partials in a fixed order
+//    (deterministic).
 //  - k_bwd_composite: one wavefront per ray walks its live samples from the
 //    back, 64 at a time, with a reverse wavefront scan for R_k and D_k; it
-//    writes dL/dc_k and dL/draw per sample.
-//  - k_mlp_bwd: per 32-sample batch, the output-layer adjoint on the vector
-//    ALUs, then W1^T and W0^T products on FP32 MFMA (transposed weight
-//    fragments in LDS); hidden-layer gradients are staged for the weight
-//    gradients and the 12 feature gradients written in brick order.
+//    writes dL/draw per sample.
 //  - k_fgrad_seg, k_fgrad_gather: the feature and raw-density gradients of
 //    each brick segment summed per tile vertex on chip, then added to the
 //    grids per vertex in a fixed order (no atomics).
-//  - k_wgrad: weight gradients as split-K MFMA products over the staged
-//    per-sample vectors, one partial per block, reduced in a fixed order by
-//    k_wgrad_apply (deterministic).
-#include "kernels.h"
+#include <algorithm>
+
+#include "mlp_common.h"
 
 namespace cic {
 
@@ -99,8 +99,6 @@ __global__ __launch_bounds__(256) void k_bwd_composite(GridK g, OptsK op, Render
             const float raw = trilerp1(dens, g, i0, fr, 1, 0);
             const float draw = ds * sigmoidf(raw + g.shift);
             bb.rec_draw[r] = draw;   // added per brick segment with the feature gradients
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) bb.rec_dc[3 * r + ch] = w * gr[ch];
         }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) carry[ch] += __shfl(incl[ch], 0, kWave);
@@ -113,142 +111,6 @@ void launch_backward_composite(const GridK &g, const OptsK &o, const RenderBufs 
 {
     if (b.n == 0) return;
     hipLaunchKernelGGL(k_bwd_composite, dim3((unsigned)((b.n + 3) / 4)), dim3(256), 0, s, g, o, b, bb);
-}
-
-// ---------------------------------------------------------------------------
-// MLP backward
-// ---------------------------------------------------------------------------
-constexpr int kBwdWaves = 8;
-constexpr int kBNT = 2;
-// LDS (floats): W1T fragments [ti 8][c4 8][lane 64][4], W0T fragments
-// [c4 8][lane 64][4], W2 [q 4][ch 3][t 8][r 4]
-constexpr int kBOffW1T = 0;
-constexpr int kBOffW0T = kBOffW1T + 8 * 8 * 64 * 4;
-constexpr int kBOffW2 = kBOffW0T + 8 * 64 * 4;
-constexpr int kBLds = kBOffW2 + 384;
-
-__global__ __launch_bounds__(kBwdWaves * 64, 1) void k_mlp_bwd(GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
-{
-    extern __shared__ float lds[];
-    const int nthr = blockDim.x;
-    for (int i = threadIdx.x; i < 8 * 8 * 64 * 4; i += nthr) {
-        const int rr = i & 3, l = (i >> 2) & 63, c4 = (i >> 8) & 7, ti = i >> 11;
-        lds[kBOffW1T + i] = m.w1[(16 * c4 + 4 * (l >> 4) + rr) * 128 + 16 * ti + (l & 15)];
-    }
-    for (int i = threadIdx.x; i < 8 * 64 * 4; i += nthr) {
-        const int rr = i & 3, l = (i >> 2) & 63, c4 = i >> 8;
-        const int col = l & 15;
-        lds[kBOffW0T + i] = col < 12 ? m.w0[(16 * c4 + 4 * (l >> 4) + rr) * 39 + col] : 0.f;
-    }
-    for (int i = threadIdx.x; i < 384; i += nthr) {
-        const int q = i / 96, ch = (i / 32) % 3, t = (i / 4) % 8, r = i & 3;
-        lds[kBOffW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
-    }
-    __syncthreads();
-
-    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
-    const int wave = threadIdx.x / 64;
-    const int64_t total = (int64_t)b.offsets[b.n];
-    const int64_t nbatch = (total + 16 * kBNT - 1) / (16 * kBNT);
-    const f4_t *w1t = (const f4_t *)(lds + kBOffW1T);
-    const f4_t *w0t = (const f4_t *)(lds + kBOffW0T);
-    const f4_t *w2l = (const f4_t *)(lds + kBOffW2);
-
-    const BatchRange br = xcd_batches(nbatch, kBwdWaves, wave);
-    for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
-        int64_t rec[kBNT];
-        bool valid[kBNT];
-        f4_t dp1[8][kBNT];
-        uint32_t h1m[kBNT];   // ReLU mask of h1: bit 4t + r for row 16t + 4q + r
-#pragma unroll
-        for (int nt = 0; nt < kBNT; ++nt) {
-            const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
-            valid[nt] = s < total;
-            rec[nt] = valid[nt] ? (int64_t)b.perm[s] : 0;
-            const uint32_t h2m = valid[nt] ? b.stage_mask[rec[nt] * 8 + 4 + q] : 0u;
-            h1m[nt] = valid[nt] ? b.stage_mask[rec[nt] * 8 + q] : 0u;
-            float dl[3] = {0.f, 0.f, 0.f};
-            if (valid[nt]) {
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float c = b.rec_c[3 * rec[nt] + ch];
-                    dl[ch] = bb.rec_dc[3 * rec[nt] + ch] * c * (1.f - c);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const f4_t wa = w2l[(q * 3 + 0) * 8 + t], wb = w2l[(q * 3 + 1) * 8 + t], wc = w2l[(q * 3 + 2) * 8 + t];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float v = fmaf(wa[r], dl[0], fmaf(wb[r], dl[1], wc[r] * dl[2]));
-                    dp1[t][nt][r] = ((h2m >> (4 * t + r)) & 1u) ? v : 0.f;
-                }
-            }
-            // dp1 itself is recomputed by the weight-gradient kernel
-            if (valid[nt]) {
-                float *wrow = b.stage + rec[nt] * kStageStride;
-                *(f4_t *)(wrow + kStDL + 4 * q) = (q == 0) ? f4_t{dl[0], dl[1], dl[2], 0.f} : f4_t{0.f, 0.f, 0.f, 0.f};
-            }
-        }
-        // dh1 = W1^T dp1, dp0 = dh1 * [h1 > 0]
-        f4_t dp0[8][kBNT];
-#pragma unroll
-        for (int ti = 0; ti < 8; ++ti)
-#pragma unroll
-            for (int nt = 0; nt < kBNT; ++nt) dp0[ti][nt] = f4_t{0.f, 0.f, 0.f, 0.f};
-        {
-            f4_t a = w1t[lane];
-#pragma unroll
-            for (int ti = 0; ti < 8; ++ti) {
-#pragma unroll
-                for (int c4 = 0; c4 < 8; ++c4) {
-                    const int nx = (ti * 8 + c4 + 1 < 64) ? (ti * 8 + c4 + 1) : (ti * 8 + c4);
-                    const f4_t an = w1t[nx * 64 + lane];
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                        for (int nt = 0; nt < kBNT; ++nt)
-                            dp0[ti][nt] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp1[c4][nt][rr], dp0[ti][nt], 0, 0, 0);
-                    a = an;
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-#pragma unroll
-        for (int ti = 0; ti < 8; ++ti)
-#pragma unroll
-            for (int nt = 0; nt < kBNT; ++nt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) dp0[ti][nt][r] = ((h1m[nt] >> (4 * ti + r)) & 1u) ? dp0[ti][nt][r] : 0.f;
-#pragma unroll
-        for (int nt = 0; nt < kBNT; ++nt)
-            if (valid[nt]) {
-                float *wrow = b.stage + rec[nt] * kStageStride;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) *(f4_t *)(wrow + kStDP0 + 16 * t + 4 * q) = dp0[t][nt];
-            }
-        // feature gradient = (W0^T dp0)[0:12], scattered to the grid
-        f4_t df[kBNT];
-#pragma unroll
-        for (int nt = 0; nt < kBNT; ++nt) df[nt] = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c4 = 0; c4 < 8; ++c4) {
-            const f4_t a = w0t[c4 * 64 + lane];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                for (int nt = 0; nt < kBNT; ++nt)
-                    df[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp0[c4][nt][rr], df[nt], 0, 0, 0);
-        }
-        // the 12 feature gradients of the sample at its position in brick order;
-        // the brick-segment kernel accumulates them
-#pragma unroll
-        for (int nt = 0; nt < kBNT; ++nt) {
-            const int64_t s = bt * (16 * kBNT) + nt * 16 + j;
-            if (valid[nt] && q < 3) *(f4_t *)(bb.df_sorted + s * 12 + 4 * q) = df[nt];
-        }
-    }
 }
 
 static int num_cus_b()
@@ -340,7 +202,7 @@ __global__ __launch_bounds__(256) void k_fgrad_seg(GridK g, RenderBufs b, Backwa
         const int cell = ((i0[0] - base[0]) * kBrick + (i0[1] - base[1])) * kBrick + (i0[2] - base[2]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) sfr[a][e] = fr[a];
-        const float *df = bb.df_sorted + (int64_t)s * 12;
+        const float *df = bb.rec_df + (int64_t)rec * 12;
 #pragma unroll
         for (int f = 0; f < 12; ++f) sv[f][e] = df[f];
         sv[12][e] = bb.rec_draw[rec];
@@ -447,48 +309,53 @@ __global__ __launch_bounds__(256) void k_fgrad_gather(GridK g, int nb0, RenderBu
 void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
     if (b.n_bricks == 0) return;
-    launch_brick_segments(b, kFgSeg, s);
+    launch_brick_segments(b, kFgSeg, false, s);
     const int64_t max_seg = fg_max_segments(b.n_bricks, b.n * (int64_t)b.n_samples);
     hipLaunchKernelGGL(k_fgrad_seg, dim3((unsigned)max_seg), dim3(256), 0, s, g, b, bb);
     const int nb0 = (int)(b.n_bricks / ((int64_t)g.nb1 * g.nb2));
     hipLaunchKernelGGL(k_fgrad_gather, dim3((unsigned)b.n_bricks), dim3(256), 0, s, g, nb0, b, bb);
 }
 
-void launch_mlp_backward(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
-{
-    const int lds = kBLds * (int)sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_mlp_bwd, dim3(num_cus_b()), dim3(kBwdWaves * 64), lds, s, g, m, b, bb);
-}
-
 // ---------------------------------------------------------------------------
-// Weight gradients: sums over samples of outer products of staged vectors,
+// MLP adjoint, fused: per batch of 16 live samples (ray order) a wavefront
+// recomputes the forward (full 40-wide layer-0 input, FP32 MFMA), forms the
+// output-logit gradient from dL/dc_k = w_k g, and runs the backward: dp1 =
+// [h2 > 0] (W2^T dlogit) on the vector ALUs, dh1 = W1^T dp1 and the feature
+// gradient (W0^T dp0)[0:12] on FP32 MFMA, dp0 = [h1 > 0] dh1.  Nothing of
+// it leaves the chip except the 12 feature gradients per sample (for the
+// brick-segment tiles).  Ray order fixes which samples each workgroup sums,
+// so the MLP gradients are the same bits on every call (in brick order the
+// bucketing's atomic cursors would decide it).  The weight gradients are
+// sums over samples of outer products,
 //   P0 = dp0^T [x|1|h1[0:8]]   (128 x 48: dW0 and, in column 39, db0)
 //   P1 = dp1^T h1              (128 x 128: dW1)
 //   P2 = dl^T h2               (16 x 128: dW2 in rows 0..2)
 //   P3 = dp1^T [x|1][32:48]    (128 x 16: db1 in column 7)
 //   P4 = dl^T [x|1][32:48]     (16 x 16: db2 in column 7)
-// one fused pass: each block owns a contiguous range of samples, stages 16
-// stored rows at a time in LDS, recomputes their dp1 there and runs all 105 output tiles on FP32 MFMA
-// (K = samples), writing one partial per block; k_wgrad_apply adds the
-// partials in block order (deterministic).
+// on FP32 MFMA with the samples as the reduction index.  Each wavefront
+// owns some of the 105 16x16 output tiles and keeps them in registers for
+// the workgroup's lifetime; the workgroup's wavefronts take turns writing
+// their batch's per-sample rows [x|1, h1, h2, dp0, dlogit, dp1] into one LDS
+// row block, and after each write every wavefront adds that block's 16
+// samples to its tiles.  One partial per workgroup, summed in a fixed order
+// by k_wgrad_apply (deterministic).  LDS: the forward's weight fragments
+// (88.6 KB), W0^T fragments for the feature gradients (8 KB), the row block
+// (37.9 KB).
 // ---------------------------------------------------------------------------
-constexpr int kWgStep = 16;
-// Padded LDS row (the stored row, then the recomputed dp1): an MFMA operand
-// read takes 16 consecutive columns of 4 consecutive rows, so a row stride of
-// 16 (mod 64) words puts the 64 lanes on 64 distinct banks.
-constexpr int kWgRow = kStDP1 + 128 + 24;
-static_assert(kWgRow % 64 == 16, "wgrad LDS row stride");
 constexpr int kWgTiles = 24 + 64 + 8 + 8 + 1;
-constexpr int kWgWaves = 8;
-constexpr int kWgTPW = (kWgTiles + kWgWaves - 1) / kWgWaves;
+constexpr int kAdjWaves = 8;
+constexpr int kAdjTPW = (kWgTiles + kAdjWaves - 1) / kAdjWaves;
+// Row of the LDS block: the staged vectors at the offsets below, padded so
+// that an MFMA operand read (16 consecutive columns of 4 consecutive rows)
+// puts the 64 lanes on 64 distinct banks (row stride 16 mod 64 words).
+constexpr int kAdjRow = kStDP1 + 128 + 24;
+static_assert(kAdjRow % 64 == 16, "adjoint LDS row stride");
+constexpr int kAOffW0T = kLdsF32;                       // [c4 8][lane 64][4]
+constexpr int kAOffRows = kAOffW0T + 8 * 64 * 4;        // [16][kAdjRow]
+constexpr int kALds = kAOffRows + 16 * kAdjRow;
 
 struct WgTile {
-    int a_col, b_col, out;   // stage columns of A and B, offset of the 16x16 tile in the partial
+    int a_col, b_col, out;   // row columns of A and B, offset of the 16x16 tile in the partial
     int ld;                  // row length of the partial matrix
 };
 
@@ -511,74 +378,245 @@ __device__ __forceinline__ WgTile wg_tile(int t)
     return {kStDL, kStX + 32, P4, 16};
 }
 
-// Two 8-wavefront blocks per CU (four wavefronts per SIMD, at most 128 VGPRs,
-// a few spilled): 1.37-1.39 ms per step against 1.42-1.43 ms with one block.
-__global__ __launch_bounds__(kWgWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_wgrad(const float *stage, const uint32_t *total_p, float *partials,
-                                               int64_t slab, const float *w2)
+// Two wavefronts per SIMD: a wavefront holds its batch's h1, h2, dp0, dp1
+// (128 VGPRs) and its output tiles (56) between its turns at the row block.
+__global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_adjoint(
+    GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
 {
-    __shared__ float rows[kWgStep * kWgRow];
-    const int lane = lane_id(), wave = threadIdx.x / 64;
-    const int64_t total = (int64_t)*total_p;
-    const int64_t s0 = (int64_t)blockIdx.x * slab;
-    const int64_t s1 = (s0 + slab < total) ? s0 + slab : total;
-    f4_t acc[kWgTPW];
+    extern __shared__ float lds[];
+    stage_weights_f32(m, lds);
+    for (int i = threadIdx.x; i < 8 * 64 * 4; i += blockDim.x) {
+        const int rr = i & 3, l = (i >> 2) & 63, c4 = i >> 8;
+        const int col = l & 15;
+        lds[kAOffW0T + i] = col < 12 ? m.w0[(16 * c4 + 4 * (l >> 4) + rr) * 39 + col] : 0.f;
+    }
+    __syncthreads();
+    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+    const int wave = threadIdx.x / 64;
+    const f2_t *w0f = (const f2_t *)(lds + kOffW0);
+    const f4_t *w1f = (const f4_t *)(lds + kOffW1);
+    const f4_t *w2l = (const f4_t *)(lds + kOffW2);
+    const f4_t *w0t = (const f4_t *)(lds + kAOffW0T);
+    float *rows = lds + kAOffRows;
+
+    // this workgroup's batches: the XCD's contiguous range, interleaved over
+    // its workgroups and wavefronts; every wavefront runs the same number of
+    // steps (the row-block turns are workgroup-wide)
+    const int64_t total = (int64_t)b.offsets[b.n];
+    const int64_t nbatch = (total + 15) / 16;
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
+    const int64_t per = (nbatch + kXcds - 1) / kXcds;
+    const int64_t lo = xcd * per, hi = lo + per < nbatch ? lo + per : nbatch;
+    const int64_t first = lo + (int64_t)slot * kAdjWaves, stride = (int64_t)nslots * kAdjWaves;
+    const int64_t steps = hi > first ? (hi - first + stride - 1) / stride : 0;
+
+    f4_t acc[kAdjTPW];
 #pragma unroll
-    for (int i = 0; i < kWgTPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
-    constexpr int kF4Row = kStageStride / 4;
-    // The rows of the next step are loaded into registers while this step's
-    // MFMAs run, then written to LDS (one step of software pipelining).
-    constexpr int kThreads = kWgWaves * 64;
-    static_assert(kThreads % 128 == 0, "dp1 fill: whole rows per pass");
-    // dp1 fill: thread t owns hidden unit t % 128 of rows t / 128, t / 128 +
-    // kThreads / 128, ...; the MLP backward's expression and mask, so the
-    // same bits (computing it while storing the rows, from a second load of
-    // the logit gradient, measured slower: 1.58 against 1.41 ms per step)
-    const int hu = threadIdx.x % 128;
-    const float w2a = w2[hu], w2b = w2[128 + hu], w2c = w2[256 + hu];
-    constexpr int kPer = (kWgStep * kF4Row + kThreads - 1) / kThreads;
-    f4_t pre[kPer];
-    auto load_step = [&](int64_t sb) {
+    for (int i = 0; i < kAdjTPW; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t st = 0; st < steps; ++st) {
+        const int64_t bt = first + st * stride + wave;
+        const int64_t s = bt * 16 + j;
+        const bool valid = bt < hi && s < total;
+        const uint32_t rec = valid ? (uint32_t)s : 0u;   // ray order
+        float x[10];
+        if (valid) {
+            sample_inputs<float, true>(g, b, rec, q, x);
+        } else {
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            const int r = e / kF4Row, c4 = e % kF4Row;
-            pre[i] = (e < kWgStep * kF4Row && sb + r < s1) ? *(const f4_t *)(stage + (sb + r) * kStageStride + 4 * c4)
-                                                            : f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < 10; ++c) x[c] = 0.f;
         }
-    };
-    load_step(s0);
-    for (int64_t sb = s0; sb < s1; sb += kWgStep) {
+        // forward: layer 0 (40 -> 128), the same products in the same order
+        // as the forward kernel's full-input path
+        f4_t h1[8];
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int e = threadIdx.x + i * kThreads;
-            if (e < kWgStep * kF4Row) *(f4_t *)(rows + (e / kF4Row) * kWgRow + 4 * (e % kF4Row)) = pre[i];
+        for (int t = 0; t < 8; ++t) h1[t] = *(const f4_t *)(lds + kOffB0 + 16 * t + 4 * q);
+#pragma unroll
+        for (int c2 = 0; c2 < 5; ++c2) {
+            f2_t a[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a[t] = w0f[(t * 5 + c2) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][e], x[2 * c2 + e], h1[t], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
-        for (int r = threadIdx.x / 128; r < kWgStep; r += kThreads / 128) {
-            float *row = rows + r * kWgRow;
-            const float v = fmaf(w2a, row[kStDL], fmaf(w2b, row[kStDL + 1], w2c * row[kStDL + 2]));
-            row[kStDP1 + hu] = row[kStH2 + hu] > 0.f ? v : 0.f;
-        }
-        __syncthreads();
-        if (sb + kWgStep < s1) load_step(sb + kWgStep);
 #pragma unroll
-        for (int kk = 0; kk < kWgStep; kk += 4) {
-            const float *rr = rows + (kk + (lane >> 4)) * kWgRow + (lane & 15);
+        for (int t = 0; t < 8; ++t)
 #pragma unroll
-            for (int i = 0; i < kWgTPW; ++i) {
-                const int t = wave + kWgWaves * i;
-                if (t < kWgTiles) {
-                    const WgTile w = wg_tile(t);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[w.a_col], rr[w.b_col], acc[i], 0, 0, 0);
+            for (int r = 0; r < 4; ++r) h1[t][r] = relu_bits(h1[t][r]);
+        // layer 1 (128 -> 128)
+        f4_t h2[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) h2[t] = *(const f4_t *)(lds + kOffB1 + 16 * t + 4 * q);
+        {
+            f4_t a[4], an[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) a[tt] = w1f[(tt * 8 + 0) * 64 + lane];
+#pragma unroll
+            for (int c4 = 0; c4 < 8; ++c4) {
+#pragma unroll
+                for (int tg = 0; tg < 2; ++tg) {
+                    const int step = c4 * 2 + tg, nx = step + 1 < 16 ? step + 1 : step;
+                    const int nc4 = nx >> 1, ntg = nx & 1;
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) an[tt] = w1f[((4 * ntg + tt) * 8 + nc4) * 64 + lane];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt)
+                            h2[4 * tg + tt] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[tt][rr], h1[c4][rr], h2[4 * tg + tt], 0, 0, 0);
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) a[tt] = an[tt];
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
-        __syncthreads();
-    }
-    float *out = partials + (int64_t)blockIdx.x * kPartialFloats;
 #pragma unroll
-    for (int i = 0; i < kWgTPW; ++i) {
-        const int t = wave + kWgWaves * i;
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h2[t][r] = relu_bits(h2[t][r]);
+        // output layer on the vector ALUs (every lane group ends with the
+        // three sums), sigmoid, and the logit gradient from dL/dc
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f4_t wa = w2l[(q * 3 + 0) * 8 + t], wb = w2l[(q * 3 + 1) * 8 + t], wc = w2l[(q * 3 + 2) * 8 + t];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                p0 = fmaf(wa[r], h2[t][r], p0);
+                p1 = fmaf(wb[r], h2[t][r], p1);
+                p2 = fmaf(wc[r], h2[t][r], p2);
+            }
+        }
+        p0 += __shfl_xor(p0, 16, kWave);
+        p1 += __shfl_xor(p1, 16, kWave);
+        p2 += __shfl_xor(p2, 16, kWave);
+        p0 += __shfl_xor(p0, 32, kWave);
+        p1 += __shfl_xor(p1, 32, kWave);
+        p2 += __shfl_xor(p2, 32, kWave);
+        // dL/dc_k = w_k g (g = dL/dC of the sample's ray); the colour is kept
+        // for the compositing adjoint, which runs next
+        float dl[3];
+        {
+            const float pp[3] = {p0, p1, p2};
+            const float w = valid ? b.rec_w[rec] : 0.f;
+            const uint32_t ray = valid ? b.rec_ray[rec] : 0u;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float c = sigmoidf(pp[ch] + lds[kOffB2 + ch]);
+                const float dc = valid ? w * bb.d_rgb[3 * (int64_t)ray + ch] : 0.f;
+                dl[ch] = dc * c * (1.f - c);
+                if (valid && q == ch) b.rec_c[3 * (int64_t)rec + ch] = c;
+            }
+        }
+        // dp1 = [h2 > 0] (W2^T dl), for output tile t (recomputed where the
+        // row block needs it rather than kept in registers)
+        auto dp1_tile = [&](int t) {
+            const f4_t wa = w2l[(q * 3 + 0) * 8 + t], wb = w2l[(q * 3 + 1) * 8 + t], wc = w2l[(q * 3 + 2) * 8 + t];
+            f4_t v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float u = fmaf(wa[r], dl[0], fmaf(wb[r], dl[1], wc[r] * dl[2]));
+                v[r] = h2[t][r] > 0.f ? u : 0.f;
+            }
+            return v;
+        };
+        // dh1 = W1^T dp1 (A fragments of W1^T read from the forward's W1
+        // layout), dp0 = [h1 > 0] dh1
+        f4_t dp0[8];
+#pragma unroll
+        for (int ti = 0; ti < 8; ++ti) dp0[ti] = f4_t{0.f, 0.f, 0.f, 0.f};
+        {
+            f4_t dp1[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) dp1[t] = dp1_tile(t);
+            // lane l needs W1[16 c4 + 4 (l / 16) + rr][16 ti + l % 16]; the
+            // next (ti, c4) step's four values are read while this step's
+            // MFMAs run
+            const float *w1l = lds + kOffW1 + (16 * ((lane & 15) >> 2) + 4 * (lane >> 4)) * 4 + (lane & 3);
+            float a[4], an[4];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) a[rr] = w1l[rr * 4];
+#pragma unroll
+            for (int idx = 0; idx < 64; ++idx) {
+                const int ti = idx >> 3, c4 = idx & 7;
+                const int nx = idx + 1 < 64 ? idx + 1 : idx, nti = nx >> 3, nc4 = nx & 7;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) an[rr] = w1l[((nc4 * 8 + nti) * 64 + rr) * 4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    dp0[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp1[c4][rr], dp0[ti], 0, 0, 0);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) a[rr] = an[rr];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll
+        for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dp0[ti][r] = h1[ti][r] > 0.f ? dp0[ti][r] : 0.f;
+        // feature gradient (W0^T dp0)[0:12] of the sample (ray order)
+        {
+            f4_t df = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c4 = 0; c4 < 8; ++c4) {
+                const f4_t a = w0t[c4 * 64 + lane];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) df = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp0[c4][rr], df, 0, 0, 0);
+            }
+            if (valid && q < 3) *(f4_t *)(bb.rec_df + (int64_t)rec * 12 + 4 * q) = df;
+        }
+        // weight gradients: the wavefronts take turns at the row block.  dp1
+        // is recomputed when the row is written (the empty asm keeps the
+        // compiler from reusing the values above, which would hold 32 more
+        // registers through the turns)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) asm volatile("" : "+v"(dl[ch]));
+        for (int turn = 0; turn < kAdjWaves; ++turn) {
+            __syncthreads();   // the previous block is consumed
+            if (wave == turn) {
+                float *row = rows + j * kAdjRow;
+#pragma unroll
+                for (int c = 0; c < 10; ++c) {
+                    const int src = l0_input(c, q);
+                    row[kStX + (src >= 0 ? src : 39)] = src >= 0 ? x[c] : 1.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    *(f4_t *)(row + kStH1 + 16 * t + 4 * q) = h1[t];
+                    *(f4_t *)(row + kStH2 + 16 * t + 4 * q) = h2[t];
+                    *(f4_t *)(row + kStDP0 + 16 * t + 4 * q) = dp0[t];
+                    *(f4_t *)(row + kStDP1 + 16 * t + 4 * q) = dp1_tile(t);
+                }
+                *(f4_t *)(row + kStDL + 4 * q) = q == 0 ? f4_t{dl[0], dl[1], dl[2], 0.f} : f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+            __syncthreads();
+            // per owned tile, the block's 16 samples in four k-steps (one
+            // address pair per tile, the k-step offsets immediate)
+            const float *rl = rows + (lane >> 4) * kAdjRow + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < kAdjTPW; ++i) {
+                const int t = wave + kAdjWaves * i;
+                if (t < kWgTiles) {
+                    const WgTile w = wg_tile(t);
+                    const float *pa = rl + w.a_col, *pb = rl + w.b_col;
+#pragma unroll
+                    for (int kk = 0; kk < 16; kk += 4)
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[kk * kAdjRow], pb[kk * kAdjRow], acc[i], 0, 0,
+                                                                      0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    float *out = bb.partials + (int64_t)blockIdx.x * kPartialFloats;
+#pragma unroll
+    for (int i = 0; i < kAdjTPW; ++i) {
+        const int t = wave + kAdjWaves * i;
         if (t < kWgTiles) {
             const WgTile w = wg_tile(t);
 #pragma unroll
@@ -651,16 +689,19 @@ __global__ __launch_bounds__(kApplyOut * kApplyGroups) void k_wgrad_apply(const 
     }
 }
 
-void launch_weight_grads(const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
+void launch_mlp_adjoint(const GridK &g, const cic_mlp &m, const RenderBufs &b, const BackwardBufs &bb, hipStream_t s)
 {
-    // sample range per block from the pass's maximum sample count
-    const int64_t max_s = b.n * (int64_t)b.n_samples;
-    const int64_t slab = ((max_s + kWgBlocks - 1) / kWgBlocks + kWgStep - 1) / kWgStep * kWgStep;
-    hipLaunchKernelGGL(k_wgrad, dim3(kWgBlocks), dim3(kWgWaves * 64), 0, s, (const float *)b.stage, b.offsets + b.n,
-                       bb.partials, slab, m.w2);
+    const int lds = kALds * (int)sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_adjoint, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr_set = true;
+    }
+    const int nblk = std::min(num_cus_b(), kWgBlocks);
+    hipLaunchKernelGGL(k_mlp_adjoint, dim3(nblk), dim3(kAdjWaves * 64), lds, s, g, m, b, bb);
     const int n_out = 128 * 39 + 128 + 128 * 128 + 3 * 128 + 128 + 3;
     hipLaunchKernelGGL(k_wgrad_apply, dim3((n_out + kApplyOut - 1) / kApplyOut), dim3(kApplyOut * kApplyGroups), 0, s,
-                       (const float *)bb.partials, kWgBlocks, bb);
+                       (const float *)bb.partials, nblk, bb);
 }
 
 }  // namespace cic

@@ -34,43 +34,10 @@ constexpr int kNT = CIC_F32_NT;
 constexpr int kMlpWaves = kNT == 1 ? 16 : 8;
 constexpr int kBatch = 16 * kNT;
 
-// float32 LDS layout (in floats)
-constexpr int kOffW0 = 0;                          // [t 8][c2 5][lane 64][2]
-constexpr int kOffW1 = kOffW0 + 8 * 5 * 64 * 2;    // [t 8][c4 8][lane 64][4]
-constexpr int kOffW2 = kOffW1 + 8 * 8 * 64 * 4;    // [q 4][ch 3][t 8][r 4]
-constexpr int kOffB0 = kOffW2 + 4 * 3 * 8 * 4;
-constexpr int kOffB1 = kOffB0 + 128;
-constexpr int kOffB2 = kOffB1 + 128;
-constexpr int kLdsF32 = kOffB2 + 4;
-
 int mlp_lds_bytes(int compute)
 {
     (void)compute;
     return kLdsF32 * (int)sizeof(float);
-}
-
-__device__ void stage_weights_f32(const cic_mlp &m, float *lds)
-{
-    const int nt = blockDim.x;
-    for (int i = threadIdx.x; i < 8 * 10 * 64; i += nt) {
-        const int l = i & 63, c = (i >> 6) % 10, t = i / 640;
-        const int row = 16 * t + (l & 15), src = l0_input(c, l >> 4);
-        lds[kOffW0 + ((t * 5 + (c >> 1)) * 64 + l) * 2 + (c & 1)] = src >= 0 ? m.w0[row * 39 + src] : 0.f;
-    }
-    for (int i = threadIdx.x; i < 8 * 32 * 64; i += nt) {
-        const int l = i & 63, c = (i >> 6) & 31, t = i >> 11;
-        const int row = 16 * t + (l & 15), col = 16 * (c >> 2) + 4 * (l >> 4) + (c & 3);
-        lds[kOffW1 + ((t * 8 + (c >> 2)) * 64 + l) * 4 + (c & 3)] = m.w1[row * 128 + col];
-    }
-    for (int i = threadIdx.x; i < 384; i += nt) {
-        const int q = i / 96, ch = (i / 32) % 3, t = (i / 4) % 8, r = i & 3;
-        lds[kOffW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
-    }
-    for (int i = threadIdx.x; i < 128; i += nt) {
-        lds[kOffB0 + i] = m.b0[i];
-        lds[kOffB1 + i] = m.b1[i];
-    }
-    if (threadIdx.x < 3) lds[kOffB2 + threadIdx.x] = m.b2[threadIdx.x];
 }
 
 // Per-ray direction term of layer 0: z0[ray][o] = b0[o] + sum_i W0[o][12+i] pe_i
@@ -122,11 +89,9 @@ void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s)
     hipLaunchKernelGGL(k_ray_embed, dim3(blocks), dim3(128), 0, s, m, b, b.z0);
 }
 
-// STAGE: also write x (with the constant-1 slot), h1 and h2 of every sample
-// to its stage row for the adjoint's weight gradients.  PET: the direction
-// half of layer 0 comes from the per-ray table (ray order), so layer 0 only
-// multiplies the 12 interpolated features.
-template <typename T, bool STAGE, bool PET>
+// PET: the direction half of layer 0 comes from the per-ray table, so layer 0
+// only multiplies the 12 interpolated features.
+template <typename T, bool PET>
 __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
     extern __shared__ float lds[];
@@ -161,14 +126,6 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             rec[nt] = valid[nt] ? (voxel ? b.perm[s] : (uint32_t)s) : 0u;
             if (valid[nt]) {
                 sample_inputs<T, !PET>(g, b, rec[nt], q, x[nt]);
-                if (STAGE) {
-                    float *row = b.stage + (int64_t)rec[nt] * kStageStride + kStX;
-#pragma unroll
-                    for (int c = 0; c < 10; ++c) {
-                        const int src = l0_input(c, q);
-                        row[src >= 0 ? src : 39] = src >= 0 ? x[nt][c] : 1.0f;
-                    }
-                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 10; ++c) x[nt][c] = 0.f;
@@ -218,29 +175,12 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        // ReLU of h1: all at once when staging, otherwise one input chunk
-        // ahead inside layer 1 so the vector work overlaps its MFMAs.
+        // ReLU of h1: one input chunk ahead inside layer 1, so the vector
+        // work overlaps its MFMAs
 #pragma unroll
-        for (int t = 0; t < (STAGE ? 8 : 1); ++t)
+        for (int nt = 0; nt < kNT; ++nt)
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) h1[t][nt][r] = relu_bits(h1[t][nt][r]);
-        if (STAGE) {
-#pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
-                if (valid[nt])
-                {
-                    uint32_t mk = 0u;
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        *(f4_t *)(b.stage + (int64_t)rec[nt] * kStageStride + kStH1 + 16 * t + 4 * q) = h1[t][nt];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) mk |= (h1[t][nt][r] > 0.f ? 1u : 0u) << (4 * t + r);
-                    }
-                    b.stage_mask[(int64_t)rec[nt] * 8 + q] = mk;
-                }
-        }
+            for (int r = 0; r < 4; ++r) h1[0][nt][r] = relu_bits(h1[0][nt][r]);
 
         // layer 1: 128 -> 128
         __builtin_amdgcn_s_setprio(2);
@@ -274,7 +214,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
                             for (int nt = 0; nt < kNT; ++nt)
                                 h2[4 * tg + tt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                     a[tt][rr], h1[c4][nt][rr], h2[4 * tg + tt][nt], 0, 0, 0);
-                    if (!STAGE && tg == 1 && c4 + 1 < 8) {
+                    if (tg == 1 && c4 + 1 < 8) {
 #pragma unroll
                         for (int nt = 0; nt < kNT; ++nt)
 #pragma unroll
@@ -287,25 +227,6 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             }
         }
 
-        if (STAGE) {
-#pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
-                if (valid[nt])
-                {
-                    uint32_t mk = 0u;
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        f4_t v = h2[t][nt];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            v[r] = relu_bits(v[r]);
-                            mk |= (v[r] > 0.f ? 1u : 0u) << (4 * t + r);
-                        }
-                        *(f4_t *)(b.stage + (int64_t)rec[nt] * kStageStride + kStH2 + 16 * t + 4 * q) = v;
-                    }
-                    b.stage_mask[(int64_t)rec[nt] * 8 + 4 + q] = mk;
-                }
-        }
         // layer 2: 128 -> 3 on the vector ALUs, then sigmoid
         __builtin_amdgcn_s_setprio(3);
 #pragma unroll
@@ -338,17 +259,17 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
     }
 }
 
-template <typename T, bool STAGE, bool PET>
+template <typename T, bool PET>
 static void launch_fwd(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
     const int lds = mlp_lds_bytes(m.compute);
     static bool attr_set = false;   // per process; the attribute is per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T, STAGE, PET>,
+        (void)hipFuncSetAttribute((const void *)k_mlp_fwd_f32<T, PET>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mlp_fwd_f32<T, STAGE, PET>), dim3(num_cus(b)), dim3(kMlpWaves * 64), lds, s, g, m, b,
+    hipLaunchKernelGGL((k_mlp_fwd_f32<T, PET>), dim3(num_cus(b)), dim3(kMlpWaves * 64), lds, s, g, m, b,
                        voxel ? 1 : 0);
 }
 
@@ -365,12 +286,7 @@ void launch_mlp_forward(const GridK &g, const cic_mlp &m, const RenderBufs &b, b
         launch_mlp_forward_bf16<T>(g, m, b, voxel, s);
         return;
     }
-    launch_fwd<T, false, true>(g, m, b, voxel, s);
-}
-
-void launch_mlp_forward_staged(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
-{
-    launch_fwd<float, true, false>(g, m, b, voxel, s);
+    launch_fwd<T, true>(g, m, b, voxel, s);
 }
 
 template void launch_mlp_forward<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);

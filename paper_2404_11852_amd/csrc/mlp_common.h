@@ -20,6 +20,43 @@ __host__ __device__ __forceinline__ int l0_input(int c, int q)
 
 __device__ __forceinline__ float pick3(int i, float a, float b, float c) { return i == 0 ? a : (i == 1 ? b : c); }
 
+// float32 weights in LDS (in floats), pre-permuted into per-lane MFMA
+// fragment order: W0 [t 8][c2 5][lane 64][2] (lane l of output tile t holds
+// row 16t + l%16 at the inputs of chunks 2*c2, 2*c2+1 of lane group l/16),
+// W1 [t 8][c4 8][lane 64][4] (row 16t + l%16, columns 16*c4 + 4*(l/16) + r),
+// W2 [q 4][ch 3][t 8][r 4] (column 16t + 4q + r of output row ch), biases.
+constexpr int kOffW0 = 0;
+constexpr int kOffW1 = kOffW0 + 8 * 5 * 64 * 2;
+constexpr int kOffW2 = kOffW1 + 8 * 8 * 64 * 4;
+constexpr int kOffB0 = kOffW2 + 4 * 3 * 8 * 4;
+constexpr int kOffB1 = kOffB0 + 128;
+constexpr int kOffB2 = kOffB1 + 128;
+constexpr int kLdsF32 = kOffB2 + 4;
+
+__device__ __forceinline__ void stage_weights_f32(const cic_mlp &m, float *lds)
+{
+    const int nt = blockDim.x;
+    for (int i = threadIdx.x; i < 8 * 10 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) % 10, t = i / 640;
+        const int row = 16 * t + (l & 15), src = l0_input(c, l >> 4);
+        lds[kOffW0 + ((t * 5 + (c >> 1)) * 64 + l) * 2 + (c & 1)] = src >= 0 ? m.w0[row * 39 + src] : 0.f;
+    }
+    for (int i = threadIdx.x; i < 8 * 32 * 64; i += nt) {
+        const int l = i & 63, c = (i >> 6) & 31, t = i >> 11;
+        const int row = 16 * t + (l & 15), col = 16 * (c >> 2) + 4 * (l >> 4) + (c & 3);
+        lds[kOffW1 + ((t * 8 + (c >> 2)) * 64 + l) * 4 + (c & 3)] = m.w1[row * 128 + col];
+    }
+    for (int i = threadIdx.x; i < 384; i += nt) {
+        const int q = i / 96, ch = (i / 32) % 3, t = (i / 4) % 8, r = i & 3;
+        lds[kOffW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
+    }
+    for (int i = threadIdx.x; i < 128; i += nt) {
+        lds[kOffB0 + i] = m.b0[i];
+        lds[kOffB1 + i] = m.b1[i];
+    }
+    if (threadIdx.x < 3) lds[kOffB2 + threadIdx.x] = m.b2[threadIdx.x];
+}
+
 // View-encoding inputs of lane group q (layer-0 chunks 3-9): direction
 // component q (q = 3 pads with 0), then sin and cos of encoding pairs
 // p = 3q..3q+2, p = 4*component + octave.
