@@ -373,7 +373,9 @@ def hash_bench(W, H, steps, dense_ms=None):
     """The multi-level encoding workload (hierarchical encodings): the same
     160^3 density grid and MLP, features from 4 levels of 3 features (32, 64,
     128, 256 cells per axis; 2^19-entry tables, the two finest levels
-    hashed), 800x800 frames in ray and voxel order."""
+    hashed), 800x800 frames in ray and voxel order, with float32 tables and
+    the FP32 MLP, then with float16 tables and the BF16 MLP (voxel order
+    stages each segment's level boxes in LDS)."""
     import synth
     import paper_2404_11852_amd as cic
     dens, _ = synth.make_scene(160, seed=0)
@@ -381,14 +383,31 @@ def hash_bench(W, H, steps, dense_ms=None):
     model = cic.Model(dens, None, synth.make_mlp(1), density_shift=synth.DENSITY_SHIFT, hash_enc=h)
     model.build_occupancy(synth.OCC_SIGMA)
     cam = camera(W, H, synth.orbit_pose(0))
+    import torch
+    bmodel = cic.Model(dens, None, synth.make_mlp(1), storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
+                       hash_enc=h, compute=cic.CIC_BF16)
+    bmodel.set_occupancy(model.occupancy)
     out = {"levels_cells": list(h["res"]), "log2_table": h["log2_size"],
            "hashed_levels": [int((r + 1) ** 3 > (1 << h["log2_size"])) for r in h["res"]]}
-    for name, order in (("ray", cic.CIC_ORDER_RAY), ("voxel", cic.CIC_ORDER_VOXEL)):
+    imgs = {}
+    for name, m, order in (("ray", model, cic.CIC_ORDER_RAY), ("voxel", model, cic.CIC_ORDER_VOXEL),
+                           ("bf16_ray", bmodel, cic.CIC_ORDER_RAY), ("bf16_voxel", bmodel, cic.CIC_ORDER_VOXEL)):
         opts = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=order)
-        t, n_eval, stages = timed_frames(model, opts, cam, steps, 2)
+        t, n_eval, stages = timed_frames(m, opts, cam, steps, 2)
         ms = 1e3 * t / steps
-        out[name] = {"ms_per_frame": ms, "samples_per_s": n_eval / t,
-                     "stage_ms": {k: v[0] / max(v[1], 1) * (v[1] / steps) for k, v in stages.items() if v[1]}}
+        sm = {k: v[0] / max(v[1], 1) * (v[1] / steps) for k, v in stages.items() if v[1]}
+        out[name] = {"ms_per_frame": ms, "samples_per_s": n_eval / t, "stage_ms": sm}
+        mlp_ms = sm.get("mlp", 0.0)
+        if mlp_ms > 0:
+            bf = name.startswith("bf16")
+            peak = 2500.0 if bf else PEAK_FP32_TFLOPS
+            ach = MLP_FLOP_PER_SAMPLE * (n_eval / steps) / (mlp_ms * 1e-3) / 1e12
+            out[name]["mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                                         "frac": ach / peak}
+        if name.startswith("bf16"):
+            imgs[name] = cic.render_frame(m, opts, cam)[0]
+    out["bf16_tables"] = "float16 (the multi-level tables), MLP in BF16"
+    out["bf16_voxel_equals_ray_order"] = bool(torch.equal(imgs["bf16_ray"], imgs["bf16_voxel"]))
     return out
 
 
@@ -613,8 +632,9 @@ def profile_run():
     """Short fixed workload for hardware-counter passes: a 1 GiB device copy
     (calibrates FETCH_SIZE / WRITE_SIZE against known bytes), then two 800x800
     frames in ray order, two in voxel order, one frame of the multi-level
-    encoding model in each order, the 8-view precision-path launches (BF16 in
-    ray and in voxel order, FP32) and one training step."""
+    encoding model in each order (float32 tables, FP32 MLP, then float16
+    tables, BF16 MLP), the 8-view precision-path launches (BF16 in ray and in
+    voxel order, FP32) and one training step."""
     import torch
     import synth
     import paper_2404_11852_amd as cic
@@ -635,6 +655,12 @@ def profile_run():
     hmodel.build_occupancy(synth.OCC_SIGMA)
     for order in (cic.CIC_ORDER_RAY, cic.CIC_ORDER_VOXEL):
         cic.render_frame(hmodel, cic.make_opts(256, 1e-4, True, order=order), cam)
+    torch.cuda.synchronize()
+    bmodel = cic.Model(dens, None, mlp, storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
+                       hash_enc=synth.make_hash_tables(30), compute=cic.CIC_BF16)
+    bmodel.set_occupancy(model.occupancy)
+    for order in (cic.CIC_ORDER_RAY, cic.CIC_ORDER_VOXEL):
+        cic.render_frame(bmodel, cic.make_opts(256, 1e-4, True, order=order), cam)
     torch.cuda.synchronize()
     precision_bench(scene, model.occupancy, 1)
     fwd_bwd_bench(1)

@@ -87,7 +87,7 @@ typedef struct {
     float box_hi[3];
     float density_shift;       /* added to the interpolated raw density before softplus */
     const void *density;       /* device, [res0][res1][res2] */
-    const void *features;      /* device, [res0][res1][res2][n_feat] */
+    const void *features;      /* device, [res0][res1][res2][n_feat], 4-byte aligned */
     const uint8_t *occupancy;  /* device, [(res0-1)(res1-1)(res2-1)], or NULL */
     /* Multi-level feature encoding (the hierarchical encodings of Sec. IV-A,
      * as a multiresolution hash grid).  hash_levels = 0: the features come
@@ -102,7 +102,7 @@ typedef struct {
     int32_t hash_levels;       /* 0 or 4 */
     int32_t hash_res[4];       /* cells per axis of each level, each in [1, 4096] */
     int32_t hash_log2_size;    /* table entries per level = 2^hash_log2_size, in [8, 24] */
-    const void *hash_tables;   /* device, [4][2^hash_log2_size][3], of type `storage` */
+    const void *hash_tables;   /* device, [4][2^hash_log2_size][3], of type `storage`, 4-byte aligned */
 } cic_grid;
 
 typedef struct {

@@ -80,6 +80,7 @@ int check_grid(const cic_grid *g)
     if (!g->density) return fail(CIC_ERR_INVALID, "grid.density is NULL");
     if (g->hash_levels == 0) {
         if (!g->features) return fail(CIC_ERR_INVALID, "grid.features is NULL");
+        if ((uintptr_t)g->features % 4) return fail(CIC_ERR_INVALID, "grid.features must be 4-byte aligned");
     } else {
         if (g->hash_levels != 4) return fail(CIC_ERR_INVALID, "grid.hash_levels=%d; must be 0 or 4", g->hash_levels);
         for (int l = 0; l < 4; ++l)
@@ -88,6 +89,8 @@ int check_grid(const cic_grid *g)
         if (g->hash_log2_size < 8 || g->hash_log2_size > 24)
             return fail(CIC_ERR_INVALID, "grid.hash_log2_size=%d outside [8,24]", g->hash_log2_size);
         if (!g->hash_tables) return fail(CIC_ERR_INVALID, "grid.hash_tables is NULL");
+        if ((uintptr_t)g->hash_tables % 4)
+            return fail(CIC_ERR_INVALID, "grid.hash_tables must be 4-byte aligned");
     }
     return CIC_OK;
 }

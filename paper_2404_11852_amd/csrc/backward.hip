@@ -339,8 +339,8 @@ void launch_feature_grads_bricks(const GridK &g, const RenderBufs &b, const Back
 // row block, and after each write every wavefront adds that block's 16
 // samples to its tiles.  One partial per workgroup, summed in a fixed order
 // by k_wgrad_apply (deterministic).  LDS: the forward's weight fragments
-// (88.6 KB), W0^T fragments for the feature gradients (8 KB), the row block
-// (37.9 KB).
+// (92.6 KB, W1 padded for its transposed reads), W0^T fragments for the
+// feature gradients (8 KB), the row block (37.9 KB).
 // ---------------------------------------------------------------------------
 constexpr int kWgTiles = 24 + 64 + 8 + 8 + 1;
 constexpr int kAdjWaves = 8;
@@ -350,7 +350,8 @@ constexpr int kAdjTPW = (kWgTiles + kAdjWaves - 1) / kAdjWaves;
 // puts the 64 lanes on 64 distinct banks (row stride 16 mod 64 words).
 constexpr int kAdjRow = kStDP1 + 128 + 24;
 static_assert(kAdjRow % 64 == 16, "adjoint LDS row stride");
-constexpr int kAOffW0T = kLdsF32;                       // [c4 8][lane 64][4]
+typedef F32Lds<true> AdjLds;                              // forward weights, W1 padded
+constexpr int kAOffW0T = AdjLds::kSize;                  // [c4 8][lane 64][4]
 constexpr int kAOffRows = kAOffW0T + 8 * 64 * 4;        // [16][kAdjRow]
 constexpr int kALds = kAOffRows + 16 * kAdjRow;
 
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
     GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
 {
     extern __shared__ float lds[];
-    stage_weights_f32(m, lds);
+    stage_weights_f32<true>(m, lds);
     for (int i = threadIdx.x; i < 8 * 64 * 4; i += blockDim.x) {
         const int rr = i & 3, l = (i >> 2) & 63, c4 = i >> 8;
         const int col = l & 15;
@@ -393,10 +394,11 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
     const int lane = lane_id(), q = lane >> 4, j = lane & 15;
     const int wave = threadIdx.x / 64;
-    const f2_t *w0f = (const f2_t *)(lds + kOffW0);
-    const f4_t *w1f = (const f4_t *)(lds + kOffW1);
-    const f4_t *w2l = (const f4_t *)(lds + kOffW2);
+    const f2_t *w0f = (const f2_t *)(lds + AdjLds::kW0);
+    const f4_t *w2l = (const f4_t *)(lds + AdjLds::kW2);
     const f4_t *w0t = (const f4_t *)(lds + kAOffW0T);
+    // this lane's W1 fragment in block 0 (block k at + k * kW1Block floats)
+    const float *w1f = lds + AdjLds::w1(0, lane);
     float *rows = lds + kAOffRows;
 
     // this workgroup's batches: the XCD's contiguous range, interleaved over
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
         // as the forward kernel's full-input path
         f4_t h1[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) h1[t] = *(const f4_t *)(lds + kOffB0 + 16 * t + 4 * q);
+        for (int t = 0; t < 8; ++t) h1[t] = *(const f4_t *)(lds + AdjLds::kB0 + 16 * t + 4 * q);
 #pragma unroll
         for (int c2 = 0; c2 < 5; ++c2) {
             f2_t a[8];
@@ -450,11 +452,11 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
         // layer 1 (128 -> 128)
         f4_t h2[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) h2[t] = *(const f4_t *)(lds + kOffB1 + 16 * t + 4 * q);
+        for (int t = 0; t < 8; ++t) h2[t] = *(const f4_t *)(lds + AdjLds::kB1 + 16 * t + 4 * q);
         {
             f4_t a[4], an[4];
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt) a[tt] = w1f[(tt * 8 + 0) * 64 + lane];
+            for (int tt = 0; tt < 4; ++tt) a[tt] = *(const f4_t *)(w1f + (tt * 8 + 0) * AdjLds::kW1Block);
 #pragma unroll
             for (int c4 = 0; c4 < 8; ++c4) {
 #pragma unroll
@@ -462,7 +464,8 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
                     const int step = c4 * 2 + tg, nx = step + 1 < 16 ? step + 1 : step;
                     const int nc4 = nx >> 1, ntg = nx & 1;
 #pragma unroll
-                    for (int tt = 0; tt < 4; ++tt) an[tt] = w1f[((4 * ntg + tt) * 8 + nc4) * 64 + lane];
+                    for (int tt = 0; tt < 4; ++tt)
+                        an[tt] = *(const f4_t *)(w1f + ((4 * ntg + tt) * 8 + nc4) * AdjLds::kW1Block);
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
             const uint32_t ray = valid ? b.rec_ray[rec] : 0u;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const float c = sigmoidf(pp[ch] + lds[kOffB2 + ch]);
+                const float c = sigmoidf(pp[ch] + lds[AdjLds::kB2 + ch]);
                 const float dc = valid ? w * bb.d_rgb[3 * (int64_t)ray + ch] : 0.f;
                 dl[ch] = dc * c * (1.f - c);
                 if (valid && q == ch) b.rec_c[3 * (int64_t)rec + ch] = c;
@@ -534,10 +537,11 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
             f4_t dp1[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) dp1[t] = dp1_tile(t);
-            // lane l needs W1[16 c4 + 4 (l / 16) + rr][16 ti + l % 16]; the
-            // next (ti, c4) step's four values are read while this step's
-            // MFMAs run
-            const float *w1l = lds + kOffW1 + (16 * ((lane & 15) >> 2) + 4 * (lane >> 4)) * 4 + (lane & 3);
+            // lane l needs W1[16 c4 + 4 (l / 16) + rr][16 ti + l % 16]: float
+            // l % 4 of lane 16 g + 4 (l / 16) + rr of block (c4, ti), g =
+            // (l % 16) / 4; the next (ti, c4) step's four values are read
+            // while this step's MFMAs run
+            const float *w1l = lds + AdjLds::w1(0, 16 * ((lane & 15) >> 2) + 4 * (lane >> 4)) + (lane & 3);
             float a[4], an[4];
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) a[rr] = w1l[rr * 4];
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
                 const int ti = idx >> 3, c4 = idx & 7;
                 const int nx = idx + 1 < 64 ? idx + 1 : idx, nti = nx >> 3, nc4 = nx & 7;
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) an[rr] = w1l[((nc4 * 8 + nti) * 64 + rr) * 4];
+                for (int rr = 0; rr < 4; ++rr) an[rr] = w1l[(nc4 * 8 + nti) * AdjLds::kW1Block + rr * 4];
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
                     dp0[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rr], dp1[c4][rr], dp0[ti], 0, 0, 0);

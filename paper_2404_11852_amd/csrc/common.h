@@ -173,14 +173,11 @@ __device__ __forceinline__ float trilerp1(const T *v, const GridK &g, const int 
     return lerpf(c0, c1, fr[0]);
 }
 
-// One level of the multi-level encoding at position x: 3 features,
-// trilinear over the level's cell (float32 locate, as the dense grid's).
-template <typename T>
-__device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x[3], float out[3])
+// Cell of level l holding position x: lower vertex index (clamped to the
+// level's cells) and fraction inside it (float32 locate, as the dense grid's).
+__device__ __forceinline__ void hash_cell(const GridK &g, int l, const float x[3], int i0[3], float fr[3])
 {
     const int N = g.hN[l];
-    int i0[3];
-    float fr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float u = (x[a] - g.lo[a]) * g.hscale[l][a];
@@ -191,24 +188,89 @@ __device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x
         fr[a] = clamp01_bits(f);
         i0[a] = i;
     }
-    const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
-    const uint32_t n1 = (uint32_t)N + 1u;
-    float v[8][3];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const uint32_t vx = (uint32_t)(i0[0] + ((c >> 2) & 1)), vy = (uint32_t)(i0[1] + ((c >> 1) & 1)),
-                       vz = (uint32_t)(i0[2] + (c & 1));
-        const uint32_t e = g.hdense[l] ? (vx * n1 + vy) * n1 + vz
-                                       : (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & g.hmask;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) v[c][f] = ldv(tab, (int64_t)e * 3 + f);
-    }
+}
+
+// Table entry of vertex (vx, vy, vz) of level l: dense index on levels whose
+// (N+1)^3 vertices fit the table, spatial hash (XOR of the coordinates times
+// per-axis primes, modulo the table size) on the others.
+__device__ __forceinline__ uint32_t hash_entry(const GridK &g, int l, uint32_t vx, uint32_t vy, uint32_t vz)
+{
+    const uint32_t n1 = (uint32_t)g.hN[l] + 1u;
+    return g.hdense[l] ? (vx * n1 + vy) * n1 + vz : (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & g.hmask;
+}
+
+// Trilinear interpolation of a cell's 8 corner values v[c][f] (corner c =
+// x bit 2, y bit 1, z bit 0), z then y then x (the order of trilerp1).
+__device__ __forceinline__ void lerp3_corners(const float v[8][3], const float fr[3], float out[3])
+{
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         const float c00 = lerpf(v[0][f], v[1][f], fr[2]), c01 = lerpf(v[2][f], v[3][f], fr[2]);
         const float c10 = lerpf(v[4][f], v[5][f], fr[2]), c11 = lerpf(v[6][f], v[7][f], fr[2]);
         out[f] = lerpf(lerpf(c00, c01, fr[1]), lerpf(c10, c11, fr[1]), fr[0]);
     }
+}
+
+// Values 3e .. 3e+2 of an array (the 3 features of entry e of a level's
+// table, or features 3q .. 3q+2 of vertex v of the dense grid, e = 4v + q).
+// float16: the 6 bytes lie in the two aligned 32-bit words from byte
+// (6e & ~3), inside the array when it is 4-byte aligned and holds a multiple
+// of 2 entries: one 64-bit load instead of three 16-bit ones.
+template <typename T> __device__ __forceinline__ void load_entry3(const T *tab, uint64_t e, float out[3]);
+template <> __device__ __forceinline__ void load_entry3<float>(const float *tab, uint64_t e, float out[3])
+{
+#pragma unroll
+    for (int f = 0; f < 3; ++f) out[f] = tab[e * 3 + f];
+}
+template <> __device__ __forceinline__ void load_entry3<__half>(const __half *tab, uint64_t e, float out[3])
+{
+    const uint32_t *w = (const uint32_t *)((const char *)tab + ((e * 6) & ~(uint64_t)3));
+    const uint32_t a = w[0], b = w[1], sh = ((uint32_t)e & 1u) * 16u;
+    const uint32_t lo = __builtin_amdgcn_alignbit(b, a, sh), hi = b >> sh;
+    out[0] = __half2float(__ushort_as_half((unsigned short)(lo & 0xffffu)));
+    out[1] = __half2float(__ushort_as_half((unsigned short)(lo >> 16)));
+    out[2] = __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu)));
+}
+
+// The 8 corners' features of cell i0 of level l, from the table.
+template <typename T>
+__device__ __forceinline__ void hash_corners(const GridK &g, int l, const int i0[3], float v[8][3])
+{
+    const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t e = hash_entry(g, l, (uint32_t)(i0[0] + ((c >> 2) & 1)), (uint32_t)(i0[1] + ((c >> 1) & 1)),
+                                      (uint32_t)(i0[2] + (c & 1)));
+        load_entry3(tab, e, v[c]);
+    }
+}
+
+// Features 3q .. 3q+2 of the dense 12-channel feature grid at cell i0.
+template <typename T>
+__device__ __forceinline__ void trilerp3(const T *feat, const GridK &g, const int i0[3], const float fr[3], int q,
+                                         float out[3])
+{
+    const int64_t sx = (int64_t)g.r1 * g.r2, sy = g.r2;
+    const int64_t b = vertex_index(g, i0[0], i0[1], i0[2]);
+    float v[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int64_t vtx = b + ((c >> 2) & 1) * sx + ((c >> 1) & 1) * sy + (c & 1);
+        load_entry3(feat, (uint64_t)(4 * vtx + q), v[c]);
+    }
+    lerp3_corners(v, fr, out);
+}
+
+// One level of the multi-level encoding at position x: 3 features,
+// trilinear over the level's cell.
+template <typename T>
+__device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x[3], float out[3])
+{
+    int i0[3];
+    float fr[3], v[8][3];
+    hash_cell(g, l, x, i0, fr);
+    hash_corners<T>(g, l, i0, v);
+    lerp3_corners(v, fr, out);
 }
 
 __device__ __forceinline__ float softplusf(float x)

@@ -45,6 +45,28 @@ void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s)
 // dependent loads that locate a sample (its record, its ray, the ray's
 // origin and direction) are issued by the whole workgroup at once.
 // ---------------------------------------------------------------------------
+// Launch shape (measured on the 8-view workload, MLP stage): a BF16 MFMA does
+// a 16-sample tile's layer in 1/16 of the FP32 time, so each batch carries
+// little MFMA work against its dependent gather loads and its weight reads
+// from LDS; 16 wavefronts per CU (128 VGPRs each) with two tiles per batch
+// hide the loads best and read each weight fragment for 32 samples
+// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms).
+#ifndef CIC_BF_NT
+#define CIC_BF_NT 2
+#endif
+
+#ifndef CIC_BF_WAVES
+#define CIC_BF_WAVES 16
+#endif
+#ifndef CIC_BF_WGS
+#define CIC_BF_WGS 1
+#endif
+constexpr int kBfWaves = CIC_BF_WAVES;   // wavefronts per workgroup
+constexpr int kBfWgs = CIC_BF_WGS;       // workgroups per CU (each holds its own 53 KB of LDS weights)
+constexpr int kBfNT = CIC_BF_NT;         // 16-sample tiles per wavefront batch
+constexpr int kBfBatch = 16 * kBfNT;
+constexpr int kTileThreads = kBfWaves * 64;   // threads of a workgroup of the LDS-tile kernels
+
 constexpr int kFTileV = kBrick + 1;
 // Channel-major tile: channel ch of vertex v at ch * kFTileS + v.  The
 // channel stride is padded so that the four 16-lane groups of a wavefront
@@ -140,10 +162,14 @@ struct TileWork {
     int64_t brick;
     uint32_t start, end;
 };
-__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w)
+struct HashSegInfo;
+__device__ void reset_bounds(HashSegInfo &h);
+__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w,
+                                              HashSegInfo *h = nullptr)
 {
     __syncthreads();   // every wave is done with the previous segment and tile
     if (threadIdx.x == 0) {
+        if (h) reset_bounds(*h);
         const int xcd = blockIdx.x % kXcds;
         const uint64_t nseg = b.seg_off[b.n_bricks];
         const uint64_t k = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, 1u);
@@ -163,6 +189,195 @@ __device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slo
 }
 
 // ---------------------------------------------------------------------------
+// Voxel order with the multi-level encoding (hierarchical encodings, Sec.
+// IV-A): the segments are still those of the density grid's bricks.  For each
+// segment the workgroup stages its samples' records (record index, ray and
+// float32 position) and reduces, per level, the bounding box of the cells the
+// samples fall in.  Levels are then taken coarse to fine: a level whose box
+// of vertices fits the LDS left over and holds no more vertices than the
+// segment's gathers would request (8 per sample) is loaded into LDS once and
+// its samples interpolate from there; the other levels (typically the finest,
+// whose box is large against the samples that use it) are gathered from the
+// table per sample, the plain data flow.  Either way a vertex's value is the
+// table's, so the features equal the ray-order gather bit for bit.
+// ---------------------------------------------------------------------------
+// Level staging rule: 0 = levels whose box fits and holds at most 8 vertices
+// per sample of the segment; 1 = the densely stored levels only, when they
+// fit; 2 = every level that fits.
+#ifndef CIC_HASH_STAGE
+#define CIC_HASH_STAGE 0
+#endif
+constexpr int kHSegWords = 5 * kTileSeg;   // record, ray, position x, y, z
+constexpr int kHTileBytes = 66 * 1024;     // LDS for the staged levels' vertices
+
+// one staged vertex: the level's 3 features and a pad, in the table's type
+template <typename T> struct HashVtx;
+template <> struct HashVtx<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <> struct HashVtx<__half> {
+    typedef _Float16 type __attribute__((ext_vector_type(4)));
+};
+
+struct HashSegInfo {
+    int lo[4][3], hi[4][3];   // per level: lowest and highest cell of the segment's samples
+    int ext[4][3];            // vertices per axis of the staged box (hi - lo + 2)
+    int off[4];               // first staged vertex of the level, -1: gathered from the table
+};
+__device__ void reset_bounds(HashSegInfo &h)
+{
+    for (int l = 0; l < 4; ++l)
+        for (int a = 0; a < 3; ++a) {
+            h.lo[l][a] = INT_MAX;
+            h.hi[l][a] = INT_MIN;
+        }
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Records of the segment's samples into LDS, and the per-level cell bounds
+// (h.lo / h.hi must hold INT_MAX / INT_MIN on entry).
+__device__ void stage_segment_hash(const GridK &g, const RenderBufs &b, uint32_t start, int n, uint32_t *seg,
+                                   HashSegInfo &h)
+{
+    int mn[4][3], mx[4][3];
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn[l][a] = INT_MAX;
+            mx[l][a] = INT_MIN;
+        }
+    constexpr int kIter = (kTileSeg + kTileThreads - 1) / kTileThreads;
+#pragma unroll
+    for (int k = 0; k < kIter; ++k) {
+        // out-of-range threads repeat the last sample (its cells do not widen the bounds)
+        const int e = (int)threadIdx.x + k * kTileThreads;
+        const uint32_t rec = b.perm[start + min(e, n - 1)];
+        SampleRay r;
+        load_sample_ray(b, b.rec_ray[rec], b.rec_k[rec], r);
+        float xp[3];
+        sample_position(r, xp);
+        if (e < n) {
+            seg[e] = rec;
+            seg[kTileSeg + e] = r.ray;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) seg[(2 + a) * kTileSeg + e] = __float_as_uint(xp[a]);
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            int i0[3];
+            float fr[3];
+            hash_cell(g, l, xp, i0, fr);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[l][a] = min(mn[l][a], i0[a]);
+                mx[l][a] = max(mx[l][a], i0[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int lo = wave_min_i(mn[l][a]), hi = wave_max_i(mx[l][a]);
+            if (lane_id() == 0 && lo <= hi) {
+                atomicMin(&h.lo[l][a], lo);
+                atomicMax(&h.hi[l][a], hi);
+            }
+        }
+}
+
+// Where the batches find a level's staged box (off < 0: not staged).
+struct LevelTile {
+    int off, lo[3], sy, sx;   // sy = ez, sx = ey * ez
+};
+
+// Which levels the segment stages, and where (one thread).
+template <typename T>
+__device__ void plan_hash_levels(const GridK &g, int n, HashSegInfo &h, LevelTile *lt)
+{
+    constexpr int64_t vb = sizeof(typename HashVtx<T>::type);
+    int64_t used = 0;
+    for (int l = 0; l < 4; ++l) {
+        int64_t nv = 1;
+        for (int a = 0; a < 3; ++a) {
+            h.ext[l][a] = h.hi[l][a] - h.lo[l][a] + 2;
+            nv *= h.ext[l][a];
+        }
+        const bool want = CIC_HASH_STAGE == 0 ? nv <= 8 * (int64_t)n : CIC_HASH_STAGE == 1 ? g.hdense[l] != 0 : true;
+        if (want && used + nv * vb <= kHTileBytes) {
+            h.off[l] = (int)(used / vb);
+            used += nv * vb;
+        } else {
+            h.off[l] = -1;
+        }
+        lt[l] = LevelTile{h.off[l], {h.lo[l][0], h.lo[l][1], h.lo[l][2]}, h.ext[l][2], h.ext[l][1] * h.ext[l][2]};
+    }
+}
+
+// The staged levels' vertex boxes from the tables into LDS (vertex (dx, dy,
+// dz) of the box at off + (dx * ey + dy) * ez + dz).
+template <typename T>
+__device__ void load_hash_tiles(const GridK &g, const HashSegInfo &h, typename HashVtx<T>::type *tile)
+{
+    typedef typename HashVtx<T>::type V;
+    typedef decltype(V{}[0]) E;
+    for (int l = 0; l < 4; ++l) {
+        if (h.off[l] < 0) continue;
+        const int ey = h.ext[l][1], ez = h.ext[l][2], nv = h.ext[l][0] * ey * ez;
+        const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const int dz = v % ez, dy = (v / ez) % ey, dx = v / (ez * ey);
+            const uint32_t e = hash_entry(g, l, (uint32_t)(h.lo[l][0] + dx), (uint32_t)(h.lo[l][1] + dy),
+                                          (uint32_t)(h.lo[l][2] + dz));
+            float x[3];
+            load_entry3(tab, e, x);
+            V w;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) w[f] = (E)x[f];
+            w[3] = (E)0.0f;
+            tile[h.off[l] + v] = w;
+        }
+    }
+}
+
+// Level q's 3 features of a sample at position xp: from the staged box when
+// the level is staged, else gathered from the table.
+template <typename T>
+__device__ __forceinline__ void hash_level3_tiled(const GridK &g, const LevelTile &lt,
+                                                  const typename HashVtx<T>::type *tile, int q, const float xp[3],
+                                                  float x[3])
+{
+    int i0[3];
+    float fr[3], v[8][3];
+    hash_cell(g, q, xp, i0, fr);
+    if (lt.off >= 0) {
+        const int base = lt.off + (i0[0] - lt.lo[0]) * lt.sx + (i0[1] - lt.lo[1]) * lt.sy + (i0[2] - lt.lo[2]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const auto w = tile[base + ((c >> 2) & 1) * lt.sx + ((c >> 1) & 1) * lt.sy + (c & 1)];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) v[c][f] = (float)w[f];
+        }
+    } else {
+        hash_corners<T>(g, q, i0, v);
+    }
+    lerp3_corners(v, fr, x);
+}
+
+// ---------------------------------------------------------------------------
 // BF16 variant: every layer on v_mfma_f32_16x16x32_bf16 (inputs rounded to
 // BF16 with round-to-nearest-even, FP32 accumulation, FP32 bias and
 // activations).  K = 32 per instruction: lane (q, j) supplies 8 consecutive
@@ -176,26 +391,6 @@ __device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slo
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-// Launch shape (measured on the 8-view workload, MLP stage): a BF16 MFMA does
-// a 16-sample tile's layer in 1/16 of the FP32 time, so each batch carries
-// little MFMA work against its dependent gather loads and its weight reads
-// from LDS; 16 wavefronts per CU (128 VGPRs each) with two tiles per batch
-// hide the loads best and read each weight fragment for 32 samples
-// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms).
-#ifndef CIC_BF_NT
-#define CIC_BF_NT 2
-#endif
-
-#ifndef CIC_BF_WAVES
-#define CIC_BF_WAVES 16
-#endif
-#ifndef CIC_BF_WGS
-#define CIC_BF_WGS 1
-#endif
-constexpr int kBfWaves = CIC_BF_WAVES;   // wavefronts per workgroup
-constexpr int kBfWgs = CIC_BF_WGS;       // workgroups per CU (each holds its own 53 KB of LDS weights)
-constexpr int kBfNT = CIC_BF_NT;         // 16-sample tiles per wavefront batch
-constexpr int kBfBatch = 16 * kBfNT;
 // LDS layout in 16-byte fragments, then floats
 constexpr int kBfW0 = 0;                           // [t 8][c 2][lane 64]
 constexpr int kBfW1 = kBfW0 + 8 * 2 * 64;          // [t 8][c 4][lane 64]
@@ -285,16 +480,24 @@ __device__ __forceinline__ float sigmoid_hw(float x)
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * x));
 }
 
-// TILE: voxel order with the brick's features staged in LDS (dense grids).
-template <typename T, bool TILE>
+// TILE: 0 = gathers from the grid (ray order, or voxel order through the
+// sample permutation); 1 = voxel order with the brick's features staged in
+// LDS (dense grids); 2 = voxel order with the segment's multi-level encoding
+// boxes staged in LDS.
+template <typename T, int TILE>
 __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
+    typedef typename HashVtx<T>::type HV;
     extern __shared__ float lds_raw[];
     bf8_t *frag = (bf8_t *)lds_raw;
     float *fl = lds_raw + kBfFrags * 4;
-    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;    // TILE only: the brick's features
-    uint32_t *seg = (uint32_t *)(tile + kFTileFloats);   // TILE only: the segment's records
+    float *tile = lds_raw + kBfFrags * 4 + kBfFloats;    // TILE 1: the brick's features
+    // TILE 1, 2: the segment's records
+    uint32_t *seg = TILE == 1 ? (uint32_t *)(tile + kFTileFloats) : (uint32_t *)tile;
+    HV *htile = (HV *)(seg + kHSegWords);                // TILE 2: the staged level boxes
     __shared__ TileWork seg_slot;
+    __shared__ HashSegInfo hinfo;
+    __shared__ LevelTile ltab[4];
     stage_weights_bf16(m, frag, fl);
     __syncthreads();
 
@@ -321,7 +524,12 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
             bf8_t ev;
             if (valid[nt]) {
                 uint32_t ray;
-                if (TILE) {
+                if constexpr (TILE == 2) {
+                    ray = seg[kTileSeg + s];
+                    const float xp[3] = {__uint_as_float(seg[2 * kTileSeg + s]), __uint_as_float(seg[3 * kTileSeg + s]),
+                                         __uint_as_float(seg[4 * kTileSeg + s])};
+                    hash_level3_tiled<T>(g, ltab[q], htile, q, xp, x);
+                } else if constexpr (TILE == 1) {
                     ray = seg[kTileSeg + s];
                     const float fr[3] = {__uint_as_float(seg[2 * kTileSeg + s]),
                                          __uint_as_float(seg[3 * kTileSeg + s]),
@@ -410,7 +618,20 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         }
     };
 
-    if (TILE) {
+    if constexpr (TILE == 2) {
+        TileWork w;
+        while (claim_segment(b, &seg_slot, w, &hinfo)) {
+            const int n = (int)(w.end - w.start);
+            stage_segment_hash(g, b, w.start, n, seg, hinfo);
+            __syncthreads();
+            if (threadIdx.x == 0) plan_hash_levels<T>(g, n, hinfo, ltab);
+            __syncthreads();
+            load_hash_tiles<T>(g, hinfo, htile);
+            __syncthreads();
+            const int nb = (n + kBfBatch - 1) / kBfBatch;
+            for (int bi = wave; bi < nb; bi += kBfWaves) batch((int64_t)bi * kBfBatch, (int64_t)n);
+        }
+    } else if constexpr (TILE == 1) {
         TileWork w;
         while (claim_segment(b, &seg_slot, w)) {
             const BrickBase base = brick_base(g, w.brick);
@@ -431,10 +652,10 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
 #ifndef CIC_VOXEL_TILE
 #define CIC_VOXEL_TILE 1
 #endif
-template <typename T, bool TILE>
+template <typename T, int TILE>
 static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
-    const int lds = kLdsBf16 + (TILE ? (kFTileFloats + kSegWords) * 4 : 0);
+    const int lds = kLdsBf16 + (TILE == 1 ? (kFTileFloats + kSegWords) * 4 : TILE == 2 ? kHSegWords * 4 + kHTileBytes : 0);
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_mlp_fwd_bf16<T, TILE>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -454,8 +675,12 @@ static void launch_bf16_k(const GridK &g, const cic_mlp &m, const RenderBufs &b,
 template <typename T>
 void launch_mlp_forward_bf16(const GridK &g, const cic_mlp &m, const RenderBufs &b, bool voxel, hipStream_t s)
 {
-    if (CIC_VOXEL_TILE && voxel && g.hlevels == 0) launch_bf16_k<T, true>(g, m, b, true, s);
-    else launch_bf16_k<T, false>(g, m, b, voxel, s);
+    if (CIC_VOXEL_TILE && voxel) {
+        if (g.hlevels == 0) launch_bf16_k<T, 1>(g, m, b, true, s);
+        else launch_bf16_k<T, 2>(g, m, b, true, s);
+    } else {
+        launch_bf16_k<T, 0>(g, m, b, voxel, s);
+    }
 }
 
 template void launch_mlp_forward_bf16<float>(const GridK &, const cic_mlp &, const RenderBufs &, bool, hipStream_t);

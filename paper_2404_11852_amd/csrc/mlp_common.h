@@ -25,36 +25,58 @@ __device__ __forceinline__ float pick3(int i, float a, float b, float c) { retur
 // row 16t + l%16 at the inputs of chunks 2*c2, 2*c2+1 of lane group l/16),
 // W1 [t 8][c4 8][lane 64][4] (row 16t + l%16, columns 16*c4 + 4*(l/16) + r),
 // W2 [q 4][ch 3][t 8][r 4] (column 16t + 4q + r of output row ch), biases.
-constexpr int kOffW0 = 0;
-constexpr int kOffW1 = kOffW0 + 8 * 5 * 64 * 2;
-constexpr int kOffW2 = kOffW1 + 8 * 8 * 64 * 4;
-constexpr int kOffB0 = kOffW2 + 4 * 3 * 8 * 4;
-constexpr int kOffB1 = kOffB0 + 128;
-constexpr int kOffB2 = kOffB1 + 128;
-constexpr int kLdsF32 = kOffB2 + 4;
+// PAD inserts 4 floats after every 16 lanes of a W1 block: the fragment reads
+// stay conflict-free, and a read of W1 transposed (lane l taking row
+// 16 c4 + 4 (l/16) + rr, column 16 ti + l%16) puts the 64 lanes on 64
+// distinct banks instead of 16.
+template <bool PAD>
+struct F32Lds {
+    static constexpr int kW1Block = PAD ? 272 : 256;
+    static constexpr int kW0 = 0;
+    static constexpr int kW1 = kW0 + 8 * 5 * 64 * 2;
+    static constexpr int kW2 = kW1 + 64 * kW1Block;
+    static constexpr int kB0 = kW2 + 4 * 3 * 8 * 4;
+    static constexpr int kB1 = kB0 + 128;
+    static constexpr int kB2 = kB1 + 128;
+    static constexpr int kSize = kB2 + 4;
+    // first float of lane `lane` of W1 block (t * 8 + c4)
+    __host__ __device__ static constexpr int w1(int blk, int lane)
+    {
+        return kW1 + blk * kW1Block + 4 * (PAD ? lane + (lane >> 4) : lane);
+    }
+};
+constexpr int kOffW0 = F32Lds<false>::kW0;
+constexpr int kOffW1 = F32Lds<false>::kW1;
+constexpr int kOffW2 = F32Lds<false>::kW2;
+constexpr int kOffB0 = F32Lds<false>::kB0;
+constexpr int kOffB1 = F32Lds<false>::kB1;
+constexpr int kOffB2 = F32Lds<false>::kB2;
+constexpr int kLdsF32 = F32Lds<false>::kSize;
 
+template <bool PAD = false>
 __device__ __forceinline__ void stage_weights_f32(const cic_mlp &m, float *lds)
 {
+    typedef F32Lds<PAD> L;
     const int nt = blockDim.x;
     for (int i = threadIdx.x; i < 8 * 10 * 64; i += nt) {
         const int l = i & 63, c = (i >> 6) % 10, t = i / 640;
         const int row = 16 * t + (l & 15), src = l0_input(c, l >> 4);
-        lds[kOffW0 + ((t * 5 + (c >> 1)) * 64 + l) * 2 + (c & 1)] = src >= 0 ? m.w0[row * 39 + src] : 0.f;
+        lds[L::kW0 + ((t * 5 + (c >> 1)) * 64 + l) * 2 + (c & 1)] = src >= 0 ? m.w0[row * 39 + src] : 0.f;
     }
     for (int i = threadIdx.x; i < 8 * 32 * 64; i += nt) {
         const int l = i & 63, c = (i >> 6) & 31, t = i >> 11;
         const int row = 16 * t + (l & 15), col = 16 * (c >> 2) + 4 * (l >> 4) + (c & 3);
-        lds[kOffW1 + ((t * 8 + (c >> 2)) * 64 + l) * 4 + (c & 3)] = m.w1[row * 128 + col];
+        lds[L::w1(t * 8 + (c >> 2), l) + (c & 3)] = m.w1[row * 128 + col];
     }
     for (int i = threadIdx.x; i < 384; i += nt) {
         const int q = i / 96, ch = (i / 32) % 3, t = (i / 4) % 8, r = i & 3;
-        lds[kOffW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
+        lds[L::kW2 + i] = m.w2[ch * 128 + 16 * t + 4 * q + r];
     }
     for (int i = threadIdx.x; i < 128; i += nt) {
-        lds[kOffB0 + i] = m.b0[i];
-        lds[kOffB1 + i] = m.b1[i];
+        lds[L::kB0 + i] = m.b0[i];
+        lds[L::kB1 + i] = m.b1[i];
     }
-    if (threadIdx.x < 3) lds[kOffB2 + threadIdx.x] = m.b2[threadIdx.x];
+    if (threadIdx.x < 3) lds[L::kB2 + threadIdx.x] = m.b2[threadIdx.x];
 }
 
 // View-encoding inputs of lane group q (layer-0 chunks 3-9): direction
@@ -97,6 +119,14 @@ __device__ __forceinline__ void load_sample_ray(const RenderBufs &b, uint32_t ra
     }
 }
 
+// Sample position o + t_k d in float32 (the march's sample point).
+__device__ __forceinline__ void sample_position(const SampleRay &r, float xp[3])
+{
+    const float tk = sample_t(r.tn, r.delta, r.k);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xp[a] = r.o[a] + tk * r.d[a];
+}
+
 // Layer-0 inputs of one sample for this lane's group q (PE = false: only
 // the three feature channels; the direction terms come from a per-ray
 // table).
@@ -105,18 +135,20 @@ __device__ __forceinline__ void sample_inputs_from(const GridK &g, const SampleR
 {
     if (g.hlevels) {
         // multi-level encoding: lane group q gathers level q
-        const float tk = sample_t(r.tn, r.delta, r.k);
         float xp[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) xp[a] = r.o[a] + tk * r.d[a];
+        sample_position(r, xp);
         hash_level3<T>(g, q, xp, x);
     } else {
         int i0[3];
         float fr[3], tk;
         sample_voxel(r.o, r.d, r.tn, r.delta, r.k, g, i0, fr, tk);
         const T *feat = (const T *)g.features;
+        if constexpr (sizeof(T) == 2) {
+            trilerp3(feat, g, i0, fr, q, x);   // float16: one 64-bit load per vertex
+        } else {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+            for (int c = 0; c < 3; ++c) x[c] = trilerp1(feat, g, i0, fr, 12, 3 * q + c);
+        }
     }
     if (!PE) {
 #pragma unroll

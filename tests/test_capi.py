@@ -63,6 +63,14 @@ def test_hash_grid_validation(L):
     assert _render(L, g, m, o) == -1 and "hash_log2_size" in L.last_error()
     g.hash_log2_size = 19
     assert _render(L, g, m, o) == -1 and "hash_tables" in L.last_error()
+    g.hash_tables = 0x4002   # float16 entries are read as aligned 32-bit words
+    assert _render(L, g, m, o) == -1 and "4-byte aligned" in L.last_error()
+
+
+def test_feature_grid_alignment(L):
+    g, m, o = _good(L)
+    g.features = 0x2002
+    assert _render(L, g, m, o) == -1 and "features must be 4-byte aligned" in L.last_error()
 
 
 def _render(L, g, m, o, n=16, ws=0x9000, ws_bytes=None):

@@ -93,6 +93,60 @@ def test_hash_bf16_against_bf16_oracle():
     assert np.quantile(err, 0.995) <= 2e-5 and err.max() <= 2e-3
 
 
+@pytest.mark.parametrize("storage", [torch.float16, torch.float32])
+def test_hash_bf16_voxel_levels_staged_equal_ray_order(storage):
+    """BF16 voxel order stages each segment's boxes of level vertices in LDS
+    (all four levels with 2^19 tables on the 160^3 grid: FP16 boxes always
+    fit, FP32 boxes of the finest level only for segments that do not span
+    their brick) and interpolates from there: the colours equal the ray-order
+    gather bit for bit."""
+    import paper_2404_11852_amd as cic
+    print_case("hash BF16 voxel vs ray, %s tables" % storage)
+    p = HashPair(storage=storage, compute=cic.CIC_BF16)
+    o, d = synth.random_rays(30000, seed=12)
+    o, d = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    a = cic.render_rays(p.gpu, cic.make_opts(256, 1e-4, True), o, d)
+    b = cic.render_rays(p.gpu, cic.make_opts(256, 1e-4, True, order=cic.CIC_ORDER_VOXEL), o, d)
+    for x, y, name in zip(a, b, ("rgb", "depth_t", "acc")):
+        assert torch.equal(x, y), name
+
+
+def test_hash_bf16_voxel_coarse_density_grid_falls_back():
+    """A 32^3 density grid: a brick spans about 8, 17, 33 and 66 cells of
+    the four levels, so the finer levels' boxes exceed the LDS and are
+    gathered from the tables, the coarse one staged where the segment's
+    samples use its vertices often enough; colours bit-exact with ray order,
+    and against the BF16 oracle."""
+    import paper_2404_11852_amd as cic
+    print_case("hash BF16 voxel vs ray, 32^3 density grid")
+    p = HashPair(res=32, compute=cic.CIC_BF16)
+    o, d = synth.random_rays(6000, seed=13)
+    go = cic.make_opts(256, 0.0, True)
+    gv = cic.make_opts(256, 0.0, True, order=cic.CIC_ORDER_VOXEL)
+    ot, dt = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    a = cic.render_rays(p.gpu, go, ot, dt)
+    b = cic.render_rays(p.gpu, gv, ot, dt)
+    for x, y, name in zip(a, b, ("rgb", "depth_t", "acc")):
+        assert torch.equal(x, y), name
+    orgb, _, _ = oracle.render_rays(p.orc, oracle.opts(256, 0.0, True), o[:1500], d[:1500])
+    err = np.abs(to_np(b[0])[:1500].astype(np.float64) - orgb).max(axis=1)
+    print("bf16 hash voxel: p99.5 %.2e max %.2e" % (np.quantile(err, 0.995), err.max()))
+    assert np.quantile(err, 0.995) <= 2e-5 and err.max() <= 2e-3
+
+
+def test_hash_bf16_voxel_frame_800():
+    """800x800 frame, FP16 tables + BF16 MLP: voxel order with staged level
+    boxes equals ray order on every pixel."""
+    import paper_2404_11852_amd as cic
+    print_case("hash BF16 frame 800x800 voxel vs ray")
+    p = HashPair(storage=torch.float16, compute=cic.CIC_BF16)
+    gc, _ = cams(800, 800, synth.orbit_pose(2))
+    a = cic.render_frame(p.gpu, cic.make_opts(256, 1e-4, True), gc)
+    b = cic.render_frame(p.gpu, cic.make_opts(256, 1e-4, True, order=cic.CIC_ORDER_VOXEL), gc)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[2], b[2])
+    assert torch.equal(torch.nan_to_num(a[1], posinf=-1), torch.nan_to_num(b[1], posinf=-1))
+
+
 def test_hash_backward_rejected():
     import paper_2404_11852_amd as cic
     p = HashPair(res=32, occupancy=False)
