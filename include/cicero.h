@@ -135,7 +135,13 @@ typedef struct {
 
 /* Bytes of workspace needed by operation `op` for `n_items` rays (render_rays,
  * render_backward) or pixels (the frame operations).  Returns 0 on invalid
- * arguments. */
+ * arguments.  render_rays, render_frame and render_backward also accept a
+ * smaller workspace, down to cic_workspace_bytes(op, 1, ...): they then run
+ * the rays in more passes of fewer rays each (per pass about 22 B (ray
+ * order) or 32 B (voxel order) per sample slot, n_samples slots per ray, and
+ * a few hundred bytes per ray), with the same results for render_rays and
+ * render_frame; render_backward adds each pass's weight gradients in turn,
+ * so their float32 sums depend on the pass size. */
 size_t cic_workspace_bytes(int op, int64_t n_items, const cic_grid *grid, const cic_opts *opts);
 
 /* Description of the calling thread's last error ("" if none). */

@@ -7,11 +7,11 @@ import torch
 
 from . import _lib
 from ._lib import (CIC_F16, CIC_F32, CIC_BF16, CIC_ORDER_RAY, CIC_ORDER_VOXEL, CicError, extrapolate_pose,
-                   make_camera, make_opts, relative_pose)
+                   make_camera, make_opts, relative_pose, set_workspace_limit)
 
 __all__ = ["Model", "make_camera", "make_opts", "CicError", "render_rays", "render_frame", "warp_frame",
            "render_frame_sparw", "render_sequence", "render_temporal", "render_frame_ds", "render_backward",
-           "generate_rays", "build_occupancy",
+           "generate_rays", "build_occupancy", "set_workspace_limit",
            "extrapolate_pose", "relative_pose", "RenderRays",
            "CIC_F32", "CIC_F16", "CIC_BF16", "CIC_ORDER_RAY", "CIC_ORDER_VOXEL"]
 

@@ -159,6 +159,24 @@ def free_workspace():
     _ws.clear()
 
 
+# Upper bound on the workspace of render_rays, render_frame and
+# render_backward (None: the size for the fewest passes); the library then
+# runs the rays in as many passes as the bound needs.
+_ws_limit = [None]
+
+
+def set_workspace_limit(nbytes=None):
+    _ws_limit[0] = None if nbytes is None else int(nbytes)
+
+
+def _pass_workspace(op, n, grid, opts, device):
+    nb = workspace_bytes(op, n, grid, opts)
+    if _ws_limit[0] is not None:
+        nb = min(nb, _ws_limit[0])
+    ws = workspace(nb, device)
+    return ws, nb
+
+
 # ---------------------------------------------------------------------------
 # struct builders
 # ---------------------------------------------------------------------------
@@ -227,19 +245,16 @@ def generate_rays(cam, pix, rays_o, rays_d):
 
 def render_rays(grid, mlp, opts, rays_o, rays_d, rgb, depth_t, acc, n_eval=None):
     n = rays_o.shape[0]
-    nb = workspace_bytes(OP_RENDER_RAYS, n, grid, opts)
-    ws = workspace(nb, rays_o.device)
+    ws, nb = _pass_workspace(OP_RENDER_RAYS, n, grid, opts, rays_o.device)
     _check(lib().render_rays(C.byref(grid), C.byref(mlp), C.byref(opts), C.c_int64(n), _ptr(rays_o),
                              _ptr(rays_d), _ptr(rgb), _ptr(depth_t), _ptr(acc), _ptr(n_eval), _ptr(ws),
-                             C.c_size_t(ws.numel()), _stream()))
+                             C.c_size_t(nb), _stream()))
 
 
 def render_frame(grid, mlp, opts, cam, rgb, depth_z, acc=None, n_eval=None):
-    nb = workspace_bytes(OP_RENDER_FRAME, cam.width * cam.height, grid, opts)
-    ws = workspace(nb, rgb.device)
+    ws, nb = _pass_workspace(OP_RENDER_FRAME, cam.width * cam.height, grid, opts, rgb.device)
     _check(lib().render_frame(C.byref(grid), C.byref(mlp), C.byref(opts), C.byref(cam), _ptr(rgb),
-                              _ptr(depth_z), _ptr(acc), _ptr(n_eval), _ptr(ws), C.c_size_t(ws.numel()),
-                              _stream()))
+                              _ptr(depth_z), _ptr(acc), _ptr(n_eval), _ptr(ws), C.c_size_t(nb), _stream()))
 
 
 def warp_frame(ref_cam, tgt_cam, T, ref_rgb, ref_depth, tgt_rgb, tgt_depth, mask, src_index=None,
@@ -274,13 +289,12 @@ def render_frame_sparw(grid, mlp, opts, ref_cam, ref_rgb, ref_depth, tgt_cam, T,
 
 def render_backward(grid, mlp, opts, rays_o, rays_d, d_rgb, d_depth_t, d_acc, grads):
     n = rays_o.shape[0]
-    nb = workspace_bytes(OP_RENDER_BACKWARD, n, grid, opts)
-    ws = workspace(nb, rays_o.device)
+    ws, nb = _pass_workspace(OP_RENDER_BACKWARD, n, grid, opts, rays_o.device)
     _check(lib().render_backward(C.byref(grid), C.byref(mlp), C.byref(opts), C.c_int64(n), _ptr(rays_o),
                                  _ptr(rays_d), _ptr(d_rgb), _ptr(d_depth_t), _ptr(d_acc),
                                  _ptr(grads["density"]), _ptr(grads["features"]), _ptr(grads["w0"]),
                                  _ptr(grads["b0"]), _ptr(grads["w1"]), _ptr(grads["b1"]), _ptr(grads["w2"]),
-                                 _ptr(grads["b2"]), _ptr(ws), C.c_size_t(ws.numel()), _stream()))
+                                 _ptr(grads["b2"]), _ptr(ws), C.c_size_t(nb), _stream()))
 
 
 def timing_enable(on=True):

@@ -203,19 +203,24 @@ RenderBufs carve_render(Carver &cv, int64_t nc, int N, int64_t n_bricks, bool vo
     b.count = cv.take<uint32_t>(nc);
     b.offsets = cv.take<uint32_t>(nc + 1);
     b.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_elems(nc));
-    b.slot_k = cv.take<uint16_t>(ns);
-    b.slot_w = cv.take<float>(ns);
+    // The per-ray slots are read for the last time by the compaction; the
+    // colours (ray order) or the sample permutation (voxel order) are written
+    // after it, so they take the same bytes.
+    const int64_t kbytes = ((2 * ns + 255) / 256) * 256, slot_bytes = kbytes + 4 * ns;
+    char *u = cv.take<char>(voxel ? slot_bytes : std::max(slot_bytes, 12 * ns));
+    b.slot_k = (uint16_t *)u;
+    b.slot_w = u ? (float *)(u + kbytes) : nullptr;
     b.rec_ray = cv.take<uint32_t>(ns);
     b.rec_k = cv.take<uint16_t>(ns);
     b.rec_w = cv.take<float>(ns);
-    b.rec_c = cv.take<float>(3 * ns);
+    b.rec_c = voxel ? cv.take<float>(3 * ns) : (float *)u;
     b.z0 = cv.take<float>(128 * nc);
     b.enc = cv.take<uint32_t>(16 * nc);
     if (voxel) {
         b.rec_key = cv.take<uint32_t>(ns);
         b.brick_off = cv.take<uint32_t>(n_bricks + 1);
         b.brick_tmp = cv.take<uint32_t>((int64_t)scan_tmp_elems(n_bricks));
-        b.perm = cv.take<uint32_t>(ns);
+        b.perm = (uint32_t *)u;
         b.work_ctr = cv.take<uint32_t>(kXcds);
         b.seg_off = cv.take<uint32_t>(n_bricks + 1);
         b.seg_brick = cv.take<uint32_t>(tile_max_segments(n_bricks, ns));
@@ -324,6 +329,33 @@ size_t bytes_for(int op, int64_t n, const cic_grid *g, const cic_opts *o)
         return 0;
     }
     return cv.off + 256;
+}
+
+// Rays per pass that a workspace of ws_bytes holds for `op` (render_rays,
+// render_frame, render_backward): the full pass (up to `cap` rays) when it
+// fits, else the largest that does (the rays then run in more passes); 0
+// when not even one ray fits.  The pass buffers grow with the pass size.
+int64_t pass_rays(int op, int64_t n, const cic_grid *g, const cic_opts *o, size_t ws_bytes, int64_t cap)
+{
+    const int64_t full = n < cap ? n : cap;
+    if (bytes_for(op, full, g, o) <= ws_bytes) return full;
+    int64_t lo = 0, hi = full;   // lo rays fit (0: none), hi do not
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (bytes_for(op, mid, g, o) <= ws_bytes) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+int check_pass(int64_t per, int op, const cic_grid *g, const cic_opts *o, void *ws, size_t ws_bytes, size_t full)
+{
+    if (per < 1)
+        return fail(CIC_ERR_WORKSPACE, "workspace too small: need at least %zu bytes (one ray per pass; %zu for the "
+                                       "fewest passes), got %zu",
+                    bytes_for(op, 1, g, o), full, ws_bytes);
+    if (!ws) return fail(CIC_ERR_INVALID, "workspace is NULL");
+    return CIC_OK;
 }
 
 // gfx950 check, once per device.
@@ -678,16 +710,18 @@ int render_rays(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts, 
     if (n_rays < 0) return fail(CIC_ERR_INVALID, "n_rays < 0");
     if (n_rays == 0) return ok();
     if (!rays_o || !rays_d || !rgb || !depth_t || !acc) return fail(CIC_ERR_INVALID, "ray or output pointer is NULL");
-    const size_t need = bytes_for(CIC_OP_RENDER_RAYS, n_rays, grid, opts);
-    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    const int64_t per = pass_rays(CIC_OP_RENDER_RAYS, n_rays, grid, opts, ws_bytes, kChunkRays);
+    if ((rc = check_pass(per, CIC_OP_RENDER_RAYS, grid, opts, ws, ws_bytes,
+                         bytes_for(CIC_OP_RENDER_RAYS, n_rays, grid, opts))))
+        return rc;
     if ((rc = check_device())) return rc;
     hipStream_t s = (hipStream_t)stream;
     const bool voxel = opts->order == CIC_ORDER_VOXEL;
     const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
     const OptsK ok_ = make_optsk(opts);
     const int64_t nb = n_bricks_of(grid);
-    for (int64_t c0 = 0; c0 < n_rays; c0 += kChunkRays) {
-        const int64_t nc = (n_rays - c0) < kChunkRays ? (n_rays - c0) : kChunkRays;
+    for (int64_t c0 = 0; c0 < n_rays; c0 += per) {
+        const int64_t nc = (n_rays - c0) < per ? (n_rays - c0) : per;
         Carver cv(align_ws(ws));
         RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, false);
         b.rays_o = rays_o + 3 * c0;
@@ -707,16 +741,18 @@ int render_frame(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *opts,
         return rc;
     if (!rgb || !depth_z) return fail(CIC_ERR_INVALID, "rgb/depth_z is NULL");
     const int64_t np = (int64_t)cam->width * cam->height;
-    const size_t need = bytes_for(CIC_OP_RENDER_FRAME, np, grid, opts);
-    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    const int64_t per = pass_rays(CIC_OP_RENDER_FRAME, np, grid, opts, ws_bytes, kChunkRays);
+    if ((rc = check_pass(per, CIC_OP_RENDER_FRAME, grid, opts, ws, ws_bytes,
+                         bytes_for(CIC_OP_RENDER_FRAME, np, grid, opts))))
+        return rc;
     if ((rc = check_device())) return rc;
     hipStream_t s = (hipStream_t)stream;
     const bool voxel = opts->order == CIC_ORDER_VOXEL;
     const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
     const OptsK ok_ = make_optsk(opts);
     const int64_t nb = n_bricks_of(grid);
-    for (int64_t c0 = 0; c0 < np; c0 += kChunkRays) {
-        const int64_t nc = (np - c0) < kChunkRays ? (np - c0) : kChunkRays;
+    for (int64_t c0 = 0; c0 < np; c0 += per) {
+        const int64_t nc = (np - c0) < per ? (np - c0) : per;
         Carver cv(align_ws(ws));
         RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, voxel, true);
         {
@@ -1015,15 +1051,17 @@ int render_backward(const cic_grid *grid, const cic_mlp *mlp, const cic_opts *op
     if (!rays_o || !rays_d || !d_rgb) return fail(CIC_ERR_INVALID, "rays or d_rgb is NULL");
     if (!d_density || !d_features || !d_w0 || !d_b0 || !d_w1 || !d_b1 || !d_w2 || !d_b2)
         return fail(CIC_ERR_INVALID, "gradient pointer is NULL");
-    const size_t need = bytes_for(CIC_OP_RENDER_BACKWARD, n_rays, grid, opts);
-    if ((rc = check_ws(need, ws, ws_bytes))) return rc;
+    const int64_t per = pass_rays(CIC_OP_RENDER_BACKWARD, n_rays, grid, opts, ws_bytes, kChunkRaysBwd);
+    if ((rc = check_pass(per, CIC_OP_RENDER_BACKWARD, grid, opts, ws, ws_bytes,
+                         bytes_for(CIC_OP_RENDER_BACKWARD, n_rays, grid, opts))))
+        return rc;
     if ((rc = check_device())) return rc;
     hipStream_t s = (hipStream_t)stream;
     const GridK gk = make_gridk(grid, opts->use_occupancy != 0);
     const OptsK ok_ = make_optsk(opts);
     const int64_t nb = n_bricks_of(grid);
-    for (int64_t c0 = 0; c0 < n_rays; c0 += kChunkRaysBwd) {
-        const int64_t nc = (n_rays - c0) < kChunkRaysBwd ? (n_rays - c0) : kChunkRaysBwd;
+    for (int64_t c0 = 0; c0 < n_rays; c0 += per) {
+        const int64_t nc = (n_rays - c0) < per ? (n_rays - c0) : per;
         Carver cv(align_ws(ws));
         RenderBufs b = carve_render(cv, nc, opts->n_samples, nb, true, false);
         BackwardBufs bb{};

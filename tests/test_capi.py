@@ -154,6 +154,23 @@ def test_workspace_sizes(L):
     assert L.workspace_bytes(99, 10, g, o) == 0
 
 
+def test_smaller_workspace_runs_more_passes(L):
+    """render_rays takes any workspace from the one-ray size up (fewer rays
+    per pass); below it the call fails before launching anything."""
+    g, m, o = _good(L)
+    one = L.workspace_bytes(L.OP_RENDER_RAYS, 1, g, o)
+    full = L.workspace_bytes(L.OP_RENDER_RAYS, 5000, g, o)
+    assert one < full
+    assert _render(L, g, m, o, n=5000, ws_bytes=one - 1) == -2
+    msg = L.last_error()
+    assert "need at least %d bytes" % one in msg and "%d for the fewest passes" % full in msg
+    # slots shared with the colours (ray order) or the sample order (voxel order)
+    ov = L.make_opts(64, order=L.CIC_ORDER_VOXEL)
+    per_ray = (L.workspace_bytes(L.OP_RENDER_RAYS, 4001, g, o) - L.workspace_bytes(L.OP_RENDER_RAYS, 1, g, o)) / 4000
+    per_ray_v = (L.workspace_bytes(L.OP_RENDER_RAYS, 4001, g, ov) - L.workspace_bytes(L.OP_RENDER_RAYS, 1, g, ov)) / 4000
+    assert abs(per_ray - (64 * 22 + 600)) < 2 and abs(per_ray_v - (64 * 32 + 600)) < 2
+
+
 def test_product_has_no_cpu_fallback():
     """The package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_2404_11852_amd")

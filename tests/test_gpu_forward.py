@@ -185,3 +185,61 @@ def test_chunking_and_determinism():
     a2 = cic.render_rays(p.gpu, go, o, d)
     for x, y in zip(a, a2):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("order", ["ray", "voxel"])
+def test_bounded_workspace_runs_more_passes(order):
+    """A workspace a third of the one-pass size: the 800x800 frame runs in
+    several passes and gives the same bits (every sample's colour and every
+    ray's sum are independent of the pass a ray falls in), as does
+    render_rays; the BF16 path too."""
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    print_case("bounded workspace, %s order" % order)
+    p = Pair(160, seed=0, occupancy=True)
+    ordk = cic.CIC_ORDER_VOXEL if order == "voxel" else cic.CIC_ORDER_RAY
+    go = cic.make_opts(256, 1e-4, True, order=ordk)
+    gc, _ = cams(800, 800, synth.orbit_pose(1))
+    full = _lib.workspace_bytes(_lib.OP_RENDER_FRAME, 800 * 800, p.gpu.grid, go)
+    ne_a = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ne_b = torch.zeros(1, dtype=torch.int64, device="cuda")
+    a = cic.render_frame(p.gpu, go, gc, n_eval=ne_a)
+    o, d = cic.generate_rays(gc)
+    ra = cic.render_rays(p.gpu, go, o[:300000].contiguous(), d[:300000].contiguous())
+    try:
+        cic.set_workspace_limit(full // 3)
+        b = cic.render_frame(p.gpu, go, gc, n_eval=ne_b)
+        rb = cic.render_rays(p.gpu, go, o[:300000].contiguous(), d[:300000].contiguous())
+    finally:
+        cic.set_workspace_limit(None)
+    for x, y, name in zip(a, b, ("rgb", "depth_z", "acc")):
+        assert torch.equal(torch.nan_to_num(x, posinf=-1), torch.nan_to_num(y, posinf=-1)), name
+    for x, y in zip(ra, rb):
+        assert torch.equal(x, y)
+    assert int(ne_a.item()) == int(ne_b.item()) > 0
+
+
+def test_bounded_workspace_backward():
+    """render_backward with a workspace for 1000 of its 8192-ray passes: the
+    gradients equal the one-pass ones up to the float32 order of the
+    per-pass weight-gradient sums."""
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    print_case("bounded workspace, backward")
+    p = Pair(64, seed=2, occupancy=True)
+    go = cic.make_opts(128, 1e-4, True)
+    o, d = synth.random_rays(4000, seed=21)
+    o, d = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    g_rgb = torch.randn(4000, 3, device="cuda", generator=torch.Generator("cuda").manual_seed(3)) * 1e-3
+    ga = cic.render_backward(p.gpu, go, o, d, g_rgb)
+    lim = _lib.workspace_bytes(_lib.OP_RENDER_BACKWARD, 1000, p.gpu.grid, go)
+    try:
+        cic.set_workspace_limit(lim)
+        gb = cic.render_backward(p.gpu, go, o, d, g_rgb)
+    finally:
+        cic.set_workspace_limit(None)
+    for k in ga:
+        scale = float(ga[k].abs().max()) + 1e-30
+        err = float((ga[k] - gb[k]).abs().max()) / scale
+        print("%s: max rel diff %.2e" % (k, err))
+        assert err < 1e-5, k
