@@ -74,30 +74,77 @@ def camera(W, H, pose):
     return cic.make_camera(W, H, f, cx, cy, synth.as_f32(pose))
 
 
-# HBM bytes of one launch of the headline MLP kernel (ray order, 800x800 frame):
-# calibrated FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 from the rocprofv3 counter
-# passes summarised in profiles/counters_cfg2_800x800.md, valid for the kernel
-# sources they were taken on (sha256 prefix of mlp.hip + mlp_common.h +
-# common.h + kernels.h).
-MLP_TRAFFIC_BYTES = 2.505e9 + 0.718e9
-MLP_TRAFFIC_SRC = "1bc9915fc79b2cbc"
-# L2 hit rate of the same launch (TCC_HIT / (TCC_HIT + TCC_MISS)), same passes
-MLP_L2_HIT = 0.854
+# Counted traffic (bytes beyond L2: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000,
+# calibrated on a 1 GiB copy) and L2 hit rate, from the rocprofv3 counter
+# passes summarised in profiles/counters_cfg2_800x800.md, per launch of:
+#   fp32       the headline MLP kernel (ray order, 800x800 frame)
+#   bf16_ray   the BF16 MLP over the 8-view pass (3 chunks), ray order
+#   bf16_voxel the same in voxel order with LDS brick tiles
+#   adjoint    the fused MLP adjoint of the 8192-ray training step
+#   backward_grid  the same step's compositing adjoint and grid-gradient kernels
+# each valid for the kernel sources it was counted on (sha256 prefix of the
+# listed files); a changed source reports None.
+COUNTED = {
+    "fp32": (2.559e9 + 0.716e9, 0.851, ("mlp.hip", "mlp_common.h", "common.h", "kernels.h"), "b672854fe79dd5a5"),
+    "bf16_ray": (13.021e9 + 5.362e9, 0.862, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
+                 "b0331eecb5858e9e"),
+    "bf16_voxel": (22.626e9 + 7.015e9, 0.341, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
+                   "b0331eecb5858e9e"),
+    "adjoint": (0.618e9 + 0.158e9, 0.298, ("backward.hip", "mlp_common.h", "common.h", "kernels.h"),
+                "9bbd24e4fa73abdf"),
+    # compositing adjoint + brick-segment gradient tiles + tile gather (one step)
+    "backward_grid": (0.323e9 + 0.008e9 + 0.240e9 + 0.307e9 + 0.689e9 + 0.212e9, None,
+                      ("backward.hip", "mlp_common.h", "common.h", "kernels.h"), "9bbd24e4fa73abdf"),
+}
 # feature bytes a sample's gather requests from the grid in the MLP kernel:
 # 8 vertices x 12 channels x 4 B (the density is gathered by the march)
 GATHER_BYTES_PER_SAMPLE = 8 * 12 * 4
 
 
-def mlp_traffic():
-    """The counted traffic per launch, or None once the kernel sources differ
-    from the ones the counters were taken on."""
+def counted(key):
+    """(bytes per launch, L2 hit) as counted, or (None, None) once the kernel
+    sources differ from the ones the counters were taken on."""
     import hashlib
+    nbytes, hit, files, src = COUNTED[key]
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_11852_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("mlp.hip", "mlp_common.h", "common.h", "kernels.h"):
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    return MLP_TRAFFIC_BYTES if h.hexdigest()[:16] == MLP_TRAFFIC_SRC else None
+    return (nbytes, hit) if h.hexdigest()[:16] == src else (None, None)
+
+
+def hbm_block(key, ms):
+    """Counted traffic of one launch and its rate against the HBM peak."""
+    nbytes, hit = counted(key)
+    if nbytes is None or ms <= 0:
+        return {"traffic": None, "hbm_frac": None, "l2_hit": None}
+    return {"traffic": nbytes, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "l2_hit": hit}
+
+
+def workspace_bench(model, opts, cam, W, H, steps):
+    """The headline frame with the workspace bounded: the library runs the
+    rays in as many passes as the bound needs (same image bits)."""
+    import torch
+    import paper_2404_11852_amd as cic
+    from paper_2404_11852_amd import _lib
+    full = _lib.workspace_bytes(_lib.OP_RENDER_FRAME, W * H, model.grid, opts)
+    one = _lib.workspace_bytes(_lib.OP_RENDER_FRAME, 1, model.grid, opts)
+    per_ray = (full - one) / (W * H - 1)
+    out = {"one_pass_bytes": full, "bytes_per_ray": per_ray}
+    ref = cic.render_frame(model, opts, cam)[0]
+    for gb in (2, 1):
+        lim = gb << 30
+        try:
+            cic.set_workspace_limit(lim)
+            t, _, _ = timed_frames(model, opts, cam, steps, 1)
+            img = cic.render_frame(model, opts, cam)[0]
+        finally:
+            cic.set_workspace_limit(None)
+        rays = int((lim - one) // per_ray) + 1
+        out["limit_%dGiB" % gb] = {"ms_per_frame": 1e3 * t / steps, "passes": -(-(W * H) // rays),
+                                   "same_image": bool(torch.equal(img, ref))}
+    return out
 
 
 def stage_rooflines(stage_ms, live, rays):
@@ -470,12 +517,12 @@ def precision_bench(scene, occ, steps):
     out["bf16_voxel_equals_ray_order"] = bool(torch.equal(imgs["bf16_voxel"], imgs["bf16"]))
     out["psnr_bf16_vs_fp32_gpu_db"] = psnr(imgs["bf16"], imgs["fp32"])
     out["max_abs_bf16_vs_fp32_gpu"] = float((imgs["bf16"] - imgs["fp32"]).abs().max().item())
-    for name in ("bf16", "bf16_voxel"):
+    for name, key in (("bf16", "bf16_ray"), ("bf16_voxel", "bf16_voxel")):
         mlp_ms = out[name]["stage_ms"].get("mlp", 0.0)
         if mlp_ms > 0:
             ach = MLP_FLOP_PER_SAMPLE * out[name]["evaluated_samples"] / (mlp_ms * 1e-3) / 1e12
-            out[name + "_mlp_roofline"] = {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
-                                           "frac": ach / 2500.0}
+            out[name + "_mlp_roofline"] = dict({"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
+                                                "frac": ach / 2500.0}, **hbm_block(key, mlp_ms))
     if os.path.exists(AMB17_GOLDEN):
         gold = np.load(AMB17_GOLDEN)
         pix = gold["pix"]
@@ -567,10 +614,16 @@ def fwd_bwd_bench(steps):
                                 "flop_per_sample": flop / max(ne, 1), "achieved": ach,
                                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                                 "whole_step_frac": flop / (out["ms_per_step"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    if sm.get("bwd_mlp", 0.0) > 0:
+        out["mfma_roofline"]["adjoint_kernel"] = dict({"stage": "bwd_mlp"}, **hbm_block("adjoint", sm["bwd_mlp"]))
     if sm.get("bwd_composite", 0.0) > 0:
+        # the stage: compositing adjoint, brick-segment gradient tiles, their
+        # gather into the grids; algorithmic bytes counted for the first only
         gbs = BWD_COMPOSITE_BYTES_PER_SAMPLE * ne / (sm["bwd_composite"] * 1e-3) / 1e9
-        out["bwd_composite_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                         "frac": gbs / PEAK_HBM_GBS}
+        out["bwd_composite_roofline"] = dict({"bound": "hbm", "stages": "compositing adjoint + grid-gradient tiles",
+                                              "achieved_compositing_bytes": gbs, "peak": PEAK_HBM_GBS,
+                                              "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS},
+                                             **hbm_block("backward_grid", sm["bwd_composite"]))
     return out
 
 
@@ -709,7 +762,7 @@ def main():
     mlp_ms, mlp_n = stages["mlp"]
     mlp_ms_per = mlp_ms / max(mlp_n, 1)
     achieved = MLP_FLOP_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e12
-    traffic = mlp_traffic()
+    traffic, l2_hit = counted("fp32")
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
     log("%.3f ms/frame, %.3g samples/s, mlp %.3f ms/launch" % (ms_step, value, mlp_ms_per))
 
@@ -750,8 +803,10 @@ def main():
                      "hbm_frac": (traffic / (mlp_ms_per * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None,
                      "gather": {"requested_bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
                                 "effective_GBs": GATHER_BYTES_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e9,
-                                "l2_hit": MLP_L2_HIT if traffic else None}},
+                                "l2_hit": l2_hit}},
     }
+    log("bounded workspace")
+    out["workspace"] = workspace_bench(model, opts, cam, W, H, max(5, args.steps // 2))
     if not args.skip_hash:
         log("multi-level encoding workload")
         out["hash_encoding"] = hash_bench(W, H, max(3, args.steps // 4))
