@@ -202,7 +202,9 @@ def mlp_input(model, feat, d):
     return x
 
 
-def render_rays(model, op, o, d, diagnostics=False):
+def render_rays(model, op, o, d, diagnostics=False, flip=False):
+    """flip=True (a model in bfloat16 mode; implies diagnostics): diag['flip']
+    as in render_pixels."""
     o, d = _f32(o), _f32(d)
     n = o.shape[0]
     rgb = np.empty((n, 3), np.float64)
@@ -211,10 +213,14 @@ def render_rays(model, op, o, d, diagnostics=False):
     ne = np.empty(n, np.int32)
     mg = np.empty(n, np.float64)
     sig = np.empty(n, np.uint64)
+    fl = np.empty(n, np.float64) if flip else None
     lib().orc_render_rays(C.byref(model.grid), C.byref(model.mlp), C.byref(op), C.c_int64(n),
-                          _p(o), _p(d), _p(rgb), _p(dep), _p(acc), _p(ne), _p(mg), _p(sig))
-    if diagnostics:
-        return rgb, dep, acc, {"n_eval": ne, "margin": mg, "relu_sig": sig}
+                          _p(o), _p(d), _p(rgb), _p(dep), _p(acc), _p(ne), _p(mg), _p(sig), _p(fl))
+    if diagnostics or flip:
+        diag = {"n_eval": ne, "margin": mg, "relu_sig": sig}
+        if flip:
+            diag["flip"] = fl
+        return rgb, dep, acc, diag
     return rgb, dep, acc
 
 

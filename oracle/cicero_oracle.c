@@ -603,15 +603,17 @@ void orc_mlp_input(const orc_mlp *m, int n_feat, int64_t n, const double *feat, 
 }
 
 /* Render a batch of rays.  rgb [n][3], depth_t [n], acc [n] (float64);
- * n_eval [n], margin [n], relu_sig [n] may be NULL. */
+ * n_eval [n], margin [n], relu_sig [n], flip [n] (the bfloat16 rounding-flip
+ * diagnostic of orc_render_pixels) may be NULL. */
 void orc_render_rays(const orc_grid *g, const orc_mlp *m, const orc_opts *op, int64_t n,
                      const float *o, const float *d, double *rgb, double *depth_t, double *acc,
-                     int32_t *n_eval, double *margin, uint64_t *relu_sig)
+                     int32_t *n_eval, double *margin, uint64_t *relu_sig, double *flip)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < n; ++r) {
         ray_out ro;
-        render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, NULL, NULL, NULL, NULL, NULL, 0);
+        render_ray(g, m, op, o + 3 * r, d + 3 * r, &ro, NULL, NULL, NULL, NULL, NULL, flip != NULL);
+        if (flip) flip[r] = ro.flip;
         for (int ch = 0; ch < 3; ++ch) rgb[3 * r + ch] = ro.rgb[ch];
         depth_t[r] = ro.depth_t;
         acc[r] = ro.acc;
