@@ -75,7 +75,7 @@ def camera(W, H, pose):
 
 
 # Counted traffic (bytes beyond L2: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000,
-# calibrated on a 1 GiB copy) and L2 hit rate, from the rocprofv3 counter
+# calibrated on a 1 GiB copy), L2 hit rate and MFMA busy fraction, from the rocprofv3 counter
 # passes summarised in profiles/counters_cfg2_800x800.md, per launch of:
 #   fp32       the headline MLP kernel (ray order, 800x800 frame)
 #   bf16_ray   the BF16 MLP over the 8-view pass (3 chunks), ray order
@@ -85,15 +85,16 @@ def camera(W, H, pose):
 # each valid for the kernel sources it was counted on (sha256 prefix of the
 # listed files); a changed source reports None.
 COUNTED = {
-    "fp32": (2.559e9 + 0.716e9, 0.851, ("mlp.hip", "mlp_common.h", "common.h", "kernels.h"), "b672854fe79dd5a5"),
-    "bf16_ray": (13.021e9 + 5.362e9, 0.862, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
+    "fp32": (2.559e9 + 0.716e9, 0.851, 0.82, ("mlp.hip", "mlp_common.h", "common.h", "kernels.h"),
+             "b672854fe79dd5a5"),
+    "bf16_ray": (13.021e9 + 5.362e9, 0.862, 0.37, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
                  "b0331eecb5858e9e"),
-    "bf16_voxel": (22.626e9 + 7.015e9, 0.341, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
+    "bf16_voxel": (22.626e9 + 7.015e9, 0.341, 0.44, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
                    "b0331eecb5858e9e"),
-    "adjoint": (0.618e9 + 0.158e9, 0.298, ("backward.hip", "mlp_common.h", "common.h", "kernels.h"),
+    "adjoint": (0.618e9 + 0.158e9, 0.298, 0.59, ("backward.hip", "mlp_common.h", "common.h", "kernels.h"),
                 "9bbd24e4fa73abdf"),
     # compositing adjoint + brick-segment gradient tiles + tile gather (one step)
-    "backward_grid": (0.323e9 + 0.008e9 + 0.240e9 + 0.307e9 + 0.689e9 + 0.212e9, None,
+    "backward_grid": (0.323e9 + 0.008e9 + 0.240e9 + 0.307e9 + 0.689e9 + 0.212e9, None, None,
                       ("backward.hip", "mlp_common.h", "common.h", "kernels.h"), "9bbd24e4fa73abdf"),
 }
 # feature bytes a sample's gather requests from the grid in the MLP kernel:
@@ -102,24 +103,25 @@ GATHER_BYTES_PER_SAMPLE = 8 * 12 * 4
 
 
 def counted(key):
-    """(bytes per launch, L2 hit) as counted, or (None, None) once the kernel
-    sources differ from the ones the counters were taken on."""
+    """(bytes per launch, L2 hit, MFMA busy) as counted, or Nones once the
+    kernel sources differ from the ones the counters were taken on."""
     import hashlib
-    nbytes, hit, files, src = COUNTED[key]
+    nbytes, hit, busy, files, src = COUNTED[key]
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_11852_amd", "csrc")
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    return (nbytes, hit) if h.hexdigest()[:16] == src else (None, None)
+    return (nbytes, hit, busy) if h.hexdigest()[:16] == src else (None, None, None)
 
 
 def hbm_block(key, ms):
     """Counted traffic of one launch and its rate against the HBM peak."""
-    nbytes, hit = counted(key)
+    nbytes, hit, busy = counted(key)
     if nbytes is None or ms <= 0:
-        return {"traffic": None, "hbm_frac": None, "l2_hit": None}
-    return {"traffic": nbytes, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "l2_hit": hit}
+        return {"traffic": None, "hbm_frac": None, "l2_hit": None, "mfma_busy": None}
+    return {"traffic": nbytes, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "l2_hit": hit,
+            "mfma_busy": busy}
 
 
 def workspace_bench(model, opts, cam, W, H, steps):
@@ -762,7 +764,7 @@ def main():
     mlp_ms, mlp_n = stages["mlp"]
     mlp_ms_per = mlp_ms / max(mlp_n, 1)
     achieved = MLP_FLOP_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e12
-    traffic, l2_hit = counted("fp32")
+    traffic, l2_hit, mfma_busy = counted("fp32")
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items() if v[1]}
     log("%.3f ms/frame, %.3g samples/s, mlp %.3f ms/launch" % (ms_step, value, mlp_ms_per))
 
@@ -803,7 +805,8 @@ def main():
                      "hbm_frac": (traffic / (mlp_ms_per * 1e-3) / 1e9 / PEAK_HBM_GBS) if traffic else None,
                      "gather": {"requested_bytes_per_sample": GATHER_BYTES_PER_SAMPLE,
                                 "effective_GBs": GATHER_BYTES_PER_SAMPLE * samples_per_frame / (mlp_ms_per * 1e-3) / 1e9,
-                                "l2_hit": l2_hit}},
+                                "l2_hit": l2_hit},
+                     "mfma_busy": mfma_busy},
     }
     log("bounded workspace")
     out["workspace"] = workspace_bench(model, opts, cam, W, H, max(5, args.steps // 2))
