@@ -384,7 +384,7 @@ __device__ __forceinline__ WgTile wg_tile(int t)
 __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_adjoint(
     GridK g, cic_mlp m, RenderBufs b, BackwardBufs bb)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     stage_weights_f32<true>(m, lds);
     for (int i = threadIdx.x; i < 8 * 64 * 4; i += blockDim.x) {
         const int rr = i & 3, l = (i >> 2) & 63, c4 = i >> 8;

@@ -94,7 +94,7 @@ void launch_ray_embed(const cic_mlp &m, const RenderBufs &b, hipStream_t s)
 template <typename T, bool PET>
 __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     stage_weights_f32(m, lds);
     __syncthreads();
 

@@ -156,20 +156,19 @@ __device__ void stage_segment(const GridK &g, const RenderBufs &b, uint32_t star
 // instead of the whole chip's in-flight window.  Thread 0 claims the
 // segment, finds its brick in the segment table and publishes it in LDS
 // (a binary search over the segment offsets per claim measured 1.5% slower
-// for the whole stage); returns false once this XCD's range is exhausted (every workgroup of the XCD then ends).  Large
-// bricks are shared by several workgroups, each staging the brick's tile.
+// for the whole stage; claiming the next segment while the current one's
+// batches run, with batches handed out through an LDS counter, measured the
+// same as this); returns false once this XCD's range is exhausted (every
+// workgroup of the XCD then ends).  Large bricks are shared by several
+// workgroups, each staging the brick's tile.
 struct TileWork {
     int64_t brick;
     uint32_t start, end;
 };
-struct HashSegInfo;
-__device__ void reset_bounds(HashSegInfo &h);
-__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w,
-                                              HashSegInfo *h = nullptr)
+__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w)
 {
     __syncthreads();   // every wave is done with the previous segment and tile
     if (threadIdx.x == 0) {
-        if (h) reset_bounds(*h);
         const int xcd = blockIdx.x % kXcds;
         const uint64_t nseg = b.seg_off[b.n_bricks];
         const uint64_t k = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, 1u);
@@ -220,45 +219,34 @@ template <> struct HashVtx<__half> {
 };
 
 struct HashSegInfo {
+    float pmin[kBfWaves][3], pmax[kBfWaves][3];   // per wavefront: bounds of its samples' positions
     int lo[4][3], hi[4][3];   // per level: lowest and highest cell of the segment's samples
     int ext[4][3];            // vertices per axis of the staged box (hi - lo + 2)
     int off[4];               // first staged vertex of the level, -1: gathered from the table
 };
-__device__ void reset_bounds(HashSegInfo &h)
-{
-    for (int l = 0; l < 4; ++l)
-        for (int a = 0; a < 3; ++a) {
-            h.lo[l][a] = INT_MAX;
-            h.hi[l][a] = INT_MIN;
-        }
-}
 
-__device__ __forceinline__ int wave_min_i(int v)
+__device__ __forceinline__ float wave_min_f(float v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
     return v;
 }
-__device__ __forceinline__ int wave_max_i(int v)
+__device__ __forceinline__ float wave_max_f(float v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
     return v;
 }
 
-// Records of the segment's samples into LDS, and the per-level cell bounds
-// (h.lo / h.hi must hold INT_MAX / INT_MIN on entry).
+// Records of the segment's samples into LDS, and each wavefront's bounds of
+// their positions.  A level's cell index along an axis is a non-decreasing
+// function of that coordinate (subtract, scale by a positive factor, floor,
+// clamp, each monotonic in float32), so the cells of the extreme coordinates
+// bound every sample's cells exactly.
 __device__ void stage_segment_hash(const GridK &g, const RenderBufs &b, uint32_t start, int n, uint32_t *seg,
                                    HashSegInfo &h)
 {
-    int mn[4][3], mx[4][3];
-#pragma unroll
-    for (int l = 0; l < 4; ++l)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            mn[l][a] = INT_MAX;
-            mx[l][a] = INT_MIN;
-        }
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     constexpr int kIter = (kTileSeg + kTileThreads - 1) / kTileThreads;
 #pragma unroll
     for (int k = 0; k < kIter; ++k) {
@@ -276,27 +264,20 @@ __device__ void stage_segment_hash(const GridK &g, const RenderBufs &b, uint32_t
             for (int a = 0; a < 3; ++a) seg[(2 + a) * kTileSeg + e] = __float_as_uint(xp[a]);
         }
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            int i0[3];
-            float fr[3];
-            hash_cell(g, l, xp, i0, fr);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                mn[l][a] = min(mn[l][a], i0[a]);
-                mx[l][a] = max(mx[l][a], i0[a]);
-            }
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], xp[a]);
+            mx[a] = fmaxf(mx[a], xp[a]);
         }
     }
+    const int wave = threadIdx.x / kWave;
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int lo = wave_min_i(mn[l][a]), hi = wave_max_i(mx[l][a]);
-            if (lane_id() == 0 && lo <= hi) {
-                atomicMin(&h.lo[l][a], lo);
-                atomicMax(&h.hi[l][a], hi);
-            }
+    for (int a = 0; a < 3; ++a) {
+        const float lo = wave_min_f(mn[a]), hi = wave_max_f(mx[a]);
+        if (lane_id() == 0) {
+            h.pmin[wave][a] = lo;
+            h.pmax[wave][a] = hi;
         }
+    }
 }
 
 // Where the batches find a level's staged box (off < 0: not staged).
@@ -309,8 +290,20 @@ template <typename T>
 __device__ void plan_hash_levels(const GridK &g, int n, HashSegInfo &h, LevelTile *lt)
 {
     constexpr int64_t vb = sizeof(typename HashVtx<T>::type);
+    float pmin[3], pmax[3];
+    for (int a = 0; a < 3; ++a) {
+        pmin[a] = h.pmin[0][a];
+        pmax[a] = h.pmax[0][a];
+        for (int w = 1; w < kBfWaves; ++w) {
+            pmin[a] = fminf(pmin[a], h.pmin[w][a]);
+            pmax[a] = fmaxf(pmax[a], h.pmax[w][a]);
+        }
+    }
     int64_t used = 0;
     for (int l = 0; l < 4; ++l) {
+        float fr[3];
+        hash_cell(g, l, pmin, h.lo[l], fr);
+        hash_cell(g, l, pmax, h.hi[l], fr);
         int64_t nv = 1;
         for (int a = 0; a < 3; ++a) {
             h.ext[l][a] = h.hi[l][a] - h.lo[l][a] + 2;
@@ -329,26 +322,38 @@ __device__ void plan_hash_levels(const GridK &g, int n, HashSegInfo &h, LevelTil
 
 // The staged levels' vertex boxes from the tables into LDS (vertex (dx, dy,
 // dz) of the box at off + (dx * ey + dy) * ez + dz).
+// The staged boxes are contiguous in level order, so staged vertex t is
+// vertex t - off[l] of the level l whose range holds t; each thread loads
+// kHLoads of them with independent loads before storing any.
+constexpr int kHLoads = 8;
 template <typename T>
 __device__ void load_hash_tiles(const GridK &g, const HashSegInfo &h, typename HashVtx<T>::type *tile)
 {
     typedef typename HashVtx<T>::type V;
     typedef decltype(V{}[0]) E;
-    for (int l = 0; l < 4; ++l) {
-        if (h.off[l] < 0) continue;
-        const int ey = h.ext[l][1], ez = h.ext[l][2], nv = h.ext[l][0] * ey * ez;
-        const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            const int dz = v % ez, dy = (v / ez) % ey, dx = v / (ez * ey);
-            const uint32_t e = hash_entry(g, l, (uint32_t)(h.lo[l][0] + dx), (uint32_t)(h.lo[l][1] + dy),
-                                          (uint32_t)(h.lo[l][2] + dz));
-            float x[3];
-            load_entry3(tab, e, x);
-            V w;
+    int end[4], tot = 0;
 #pragma unroll
-            for (int f = 0; f < 3; ++f) w[f] = (E)x[f];
-            w[3] = (E)0.0f;
-            tile[h.off[l] + v] = w;
+    for (int l = 0; l < 4; ++l) {
+        if (h.off[l] >= 0) tot = h.off[l] + h.ext[l][0] * h.ext[l][1] * h.ext[l][2];
+        end[l] = tot;
+    }
+    for (int t0 = threadIdx.x; t0 < tot; t0 += kHLoads * kTileThreads) {
+        float x[kHLoads][3];
+#pragma unroll
+        for (int u = 0; u < kHLoads; ++u) {
+            const int t = min(t0 + u * kTileThreads, tot - 1);   // past the end: reload the last vertex
+            const int l = t < end[0] ? 0 : t < end[1] ? 1 : t < end[2] ? 2 : 3;
+            const int v = t - h.off[l], ey = h.ext[l][1], ez = h.ext[l][2];
+            const int dz = v % ez, dy = (v / ez) % ey, dx = v / (ez * ey);
+            const T *tab = (const T *)g.htab + (size_t)l * ((size_t)g.hmask + 1) * 3;
+            load_entry3(tab, hash_entry(g, l, (uint32_t)(h.lo[l][0] + dx), (uint32_t)(h.lo[l][1] + dy),
+                                        (uint32_t)(h.lo[l][2] + dz)),
+                        x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kHLoads; ++u) {
+            const int t = t0 + u * kTileThreads;
+            if (t < tot) tile[t] = V{(E)x[u][0], (E)x[u][1], (E)x[u][2], (E)0.0f};
         }
     }
 }
@@ -488,7 +493,7 @@ template <typename T, int TILE>
 __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp m, RenderBufs b, int voxel)
 {
     typedef typename HashVtx<T>::type HV;
-    extern __shared__ float lds_raw[];
+    extern __shared__ __attribute__((aligned(16))) float lds_raw[];   // 16-byte fragments
     bf8_t *frag = (bf8_t *)lds_raw;
     float *fl = lds_raw + kBfFrags * 4;
     float *tile = lds_raw + kBfFrags * 4 + kBfFloats;    // TILE 1: the brick's features
@@ -618,26 +623,21 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         }
     };
 
-    if constexpr (TILE == 2) {
-        TileWork w;
-        while (claim_segment(b, &seg_slot, w, &hinfo)) {
-            const int n = (int)(w.end - w.start);
-            stage_segment_hash(g, b, w.start, n, seg, hinfo);
-            __syncthreads();
-            if (threadIdx.x == 0) plan_hash_levels<T>(g, n, hinfo, ltab);
-            __syncthreads();
-            load_hash_tiles<T>(g, hinfo, htile);
-            __syncthreads();
-            const int nb = (n + kBfBatch - 1) / kBfBatch;
-            for (int bi = wave; bi < nb; bi += kBfWaves) batch((int64_t)bi * kBfBatch, (int64_t)n);
-        }
-    } else if constexpr (TILE == 1) {
+    if constexpr (TILE != 0) {
         TileWork w;
         while (claim_segment(b, &seg_slot, w)) {
-            const BrickBase base = brick_base(g, w.brick);
             const int n = (int)(w.end - w.start);
-            load_feature_tile<T>(g, base, tile);
-            stage_segment(g, b, w.start, n, base, seg);
+            if constexpr (TILE == 2) {
+                stage_segment_hash(g, b, w.start, n, seg, hinfo);
+                __syncthreads();
+                if (threadIdx.x == 0) plan_hash_levels<T>(g, n, hinfo, ltab);
+                __syncthreads();
+                load_hash_tiles<T>(g, hinfo, htile);
+            } else {
+                const BrickBase base = brick_base(g, w.brick);
+                load_feature_tile<T>(g, base, tile);
+                stage_segment(g, b, w.start, n, base, seg);
+            }
             __syncthreads();
             const int nb = (n + kBfBatch - 1) / kBfBatch;
             for (int bi = wave; bi < nb; bi += kBfWaves) batch((int64_t)bi * kBfBatch, (int64_t)n);
