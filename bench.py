@@ -339,6 +339,26 @@ def sparw_sweep(model, opts, W, H, windows=(6, 16, 26), angles=(0.0, 8.0, 4.0, 2
     return base
 
 
+def sparw_bf16(scene, occ, W, H):
+    """The 32-frame SpaRW orbit (window 16) with the precision path: FP16
+    grids and the BF16 MLP, in ray and in voxel order; PSNR against the same
+    model's full renders."""
+    import torch
+    import synth
+    import paper_2404_11852_amd as cic
+    dens, feats, mlp = scene
+    m = cic.Model(dens, feats, mlp, device="cuda:0", storage=torch.float16, density_shift=synth.DENSITY_SHIFT,
+                  compute=cic.CIC_BF16)
+    m.set_occupancy(occ)
+    out = {}
+    for name, order in (("ray", cic.CIC_ORDER_RAY), ("voxel", cic.CIC_ORDER_VOXEL)):
+        r, _ = sparw_orbit(m, cic.make_opts(256, 1e-4, True, order=order), W, H, n_frames=32, ref_every=16)
+        out[name] = {k: r[k] for k in ("fps", "ms_per_target", "fps_full_render", "speedup_vs_full",
+                                       "mask_fraction_mean", "psnr_vs_full_mean_db", "psnr_vs_full_min_db",
+                                       "stage_ms_per_target")}
+    return out
+
+
 def sequence_bench(model, opts, W, H, n_frames=65, window=16):
     """Off-trajectory references (Eq. 5-6) over an orbit: the two-stream
     schedule against the serial one, and the paper's lead of half a window
@@ -816,6 +836,9 @@ def main():
     if not args.skip_sparw:
         log("SpaRW orbit")
         out["sparw"] = sparw_sweep(model, opts, W, H)
+    if not args.skip_sparw:
+        log("SpaRW orbit, FP16 grid + BF16 MLP")
+        out["sparw_bf16"] = sparw_bf16(scene, model.occupancy, W, H)
     if not args.skip_sparw:
         log("off-trajectory references, serial vs two streams")
         out["sequence"] = sequence_bench(model, opts, W, H)
