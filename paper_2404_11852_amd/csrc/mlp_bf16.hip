@@ -161,24 +161,48 @@ __device__ void stage_segment(const GridK &g, const RenderBufs &b, uint32_t star
 // same as this); returns false once this XCD's range is exhausted (every
 // workgroup of the XCD then ends).  Large bricks are shared by several
 // workgroups, each staging the brick's tile.
+// With dense brick tiles, segments are claimed kClaimRun consecutive ones at
+// a time, so a brick's segments tend to follow each other in one workgroup,
+// which then keeps the brick's staged tile (reuse set) instead of loading it
+// again (measured on the 8-view pass: 24.4 ms one at a time, 24.1 ms in runs
+// of 2, 23.9 ms in runs of 8).  The multi-level boxes depend on each
+// segment's samples, so those segments are claimed one at a time.
+#ifndef CIC_CLAIM_RUN
+#define CIC_CLAIM_RUN 8
+#endif
+constexpr int kClaimRun = CIC_CLAIM_RUN;
 struct TileWork {
     int64_t brick;
     uint32_t start, end;
+    int reuse;   // the staged tile is already this brick's
 };
-__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, TileWork &w)
+// the claiming thread's state: next index of its current run, the run's end, the brick in the tile
+struct ClaimState {
+    uint64_t next, end;
+    int64_t tile_brick;
+};
+template <int RUN>
+__device__ __forceinline__ bool claim_segment(const RenderBufs &b, TileWork *slot, ClaimState &cs, TileWork &w)
 {
     __syncthreads();   // every wave is done with the previous segment and tile
     if (threadIdx.x == 0) {
         const int xcd = blockIdx.x % kXcds;
         const uint64_t nseg = b.seg_off[b.n_bricks];
-        const uint64_t k = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, 1u);
-        TileWork t{-1, 0u, 0u};
-        if (k < nseg * (xcd + 1) / kXcds) {
+        const uint64_t hi = nseg * (xcd + 1) / kXcds;
+        if (cs.next >= cs.end) {
+            cs.next = nseg * xcd / kXcds + atomicAdd(b.work_ctr + xcd, (uint32_t)RUN);
+            cs.end = min(cs.next + RUN, hi);
+        }
+        TileWork t{-1, 0u, 0u, 0};
+        if (cs.next < cs.end) {
+            const uint64_t k = cs.next++;
             const uint32_t brick = b.seg_brick[k];   // from the segment table
             const uint32_t bstart = brick == 0 ? 0u : b.brick_off[brick - 1], bend = b.brick_off[brick];
             t.brick = brick;
             t.start = bstart + ((uint32_t)k - b.seg_off[brick]) * (uint32_t)kTileSeg;
             t.end = min(bend, t.start + (uint32_t)kTileSeg);
+            t.reuse = (int64_t)brick == cs.tile_brick;
+            cs.tile_brick = brick;
         }
         *slot = t;
     }
@@ -625,7 +649,8 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
 
     if constexpr (TILE != 0) {
         TileWork w;
-        while (claim_segment(b, &seg_slot, w)) {
+        ClaimState cs{0, 0, -1};   // used by thread 0 only
+        while (claim_segment<TILE == 1 ? kClaimRun : 1>(b, &seg_slot, cs, w)) {
             const int n = (int)(w.end - w.start);
             if constexpr (TILE == 2) {
                 stage_segment_hash(g, b, w.start, n, seg, hinfo);
@@ -635,7 +660,7 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
                 load_hash_tiles<T>(g, hinfo, htile);
             } else {
                 const BrickBase base = brick_base(g, w.brick);
-                load_feature_tile<T>(g, base, tile);
+                if (!w.reuse) load_feature_tile<T>(g, base, tile);
                 stage_segment(g, b, w.start, n, base, seg);
             }
             __syncthreads();
