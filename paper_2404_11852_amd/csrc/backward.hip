@@ -600,7 +600,10 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
             }
             __syncthreads();
             // per owned tile, the block's 16 samples in four k-steps (one
-            // address pair per tile, the k-step offsets immediate)
+            // address pair per tile, the k-step offsets immediate); the
+            // compiler may start the next tiles' operand reads during these
+            // MFMAs (with a scheduling barrier per tile the adjoint kernel
+            // took 3.02 against 2.94 ms per 8192-ray step)
             const float *rl = rows + (lane >> 4) * kAdjRow + (lane & 15);
 #pragma unroll
             for (int i = 0; i < kAdjTPW; ++i) {
@@ -613,7 +616,6 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
                         acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[kk * kAdjRow], pb[kk * kAdjRow], acc[i], 0, 0,
                                                                       0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
