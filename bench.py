@@ -181,8 +181,8 @@ def stage_rooflines(stage_ms, live, rays):
 
 def measure_peaks():
     """On-box check of the published peaks the fractions use: a 2 GiB
-    device-to-device copy (read + write bytes per second) and an 8192^3
-    float32 matrix product through torch."""
+    device-to-device copy (read + write bytes per second) and 8192^3 float32
+    and bfloat16 matrix products through torch."""
     import torch
     out = {}
     src = torch.empty(1 << 29, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -207,6 +207,16 @@ def measure_peaks():
     b.record()
     torch.cuda.synchronize()
     out["fp32_gemm_TFs"] = 5 * 2 * 8192 ** 3 / (a.elapsed_time(b) * 1e-3) / 1e12
+    # the same product in bfloat16 (2-D, contiguous operands)
+    mb, nb = m.to(torch.bfloat16).contiguous(), n.to(torch.bfloat16).contiguous()
+    for _ in range(3):
+        torch.mm(mb, nb)
+    a.record()
+    for _ in range(10):
+        torch.mm(mb, nb)
+    b.record()
+    torch.cuda.synchronize()
+    out["bf16_gemm_TFs"] = 10 * 2 * 8192 ** 3 / (a.elapsed_time(b) * 1e-3) / 1e12
     out["published"] = {"hbm_GBs": PEAK_HBM_GBS, "fp32_mfma_TFs": PEAK_FP32_TFLOPS, "bf16_mfma_TFs": 2500.0}
     return out
 

@@ -123,13 +123,11 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
         for (int nt = 0; nt < kNT; ++nt) {
             const int64_t s = bt * kBatch + nt * 16 + j;
             valid[nt] = s < total;
-            rec[nt] = valid[nt] ? (voxel ? b.perm[s] : (uint32_t)s) : 0u;
-            if (valid[nt]) {
-                sample_inputs<T, !PET>(g, b, rec[nt], q, x[nt]);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 10; ++c) x[nt][c] = 0.f;
-            }
+            // a lane past the last sample works on sample 0 (in-bounds
+            // inputs, no branches around the loads); its colour is not stored
+            const int64_t sv = valid[nt] ? s : 0;
+            rec[nt] = voxel ? b.perm[sv] : (uint32_t)sv;
+            sample_inputs<T, !PET>(g, b, rec[nt], q, x[nt]);
         }
 
         // layer 0: 40 -> 128 (PET: 12 -> 128 on top of the per-ray term)
@@ -138,11 +136,10 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
         if (PET) {
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) {
-                const uint32_t zray = valid[nt] ? b.rec_ray[rec[nt]] : 0u;
-                const float *zr = b.z0 + (int64_t)zray * 128 + 4 * q;
+                // (every record's ray has live samples, so its row is written)
+                const float *zr = b.z0 + (int64_t)b.rec_ray[rec[nt]] * 128 + 4 * q;
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    h1[t][nt] = valid[nt] ? *(const f4_t *)(zr + 16 * t) : f4_t{0.f, 0.f, 0.f, 0.f};
+                for (int t = 0; t < 8; ++t) h1[t][nt] = *(const f4_t *)(zr + 16 * t);
             }
         } else {
 #pragma unroll

@@ -588,36 +588,31 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
         for (int nt = 0; nt < kBfNT; ++nt) {
             const int64_t s = s0 + nt * 16 + j;
             valid[nt] = s < send;
-            if (TILE) rec[nt] = valid[nt] ? (int64_t)seg[s] : 0;
-            else rec[nt] = valid[nt] ? (voxel ? (int64_t)b.perm[s] : s) : 0;
+            // a lane past the batch's last sample works on the first sample of
+            // the range (in-bounds inputs, no branches around the loads); its
+            // colour is not stored
+            const int64_t sv = valid[nt] ? s : 0;
+            if (TILE) rec[nt] = (int64_t)seg[sv];
+            else rec[nt] = voxel ? (int64_t)b.perm[sv] : sv;
             float x[10];
-            bf8_t ev;
-            if (valid[nt]) {
-                uint32_t ray;
-                if constexpr (TILE == 2) {
-                    ray = seg[kTileSeg + s];
-                    const float xp[3] = {__uint_as_float(seg[2 * kTileSeg + s]), __uint_as_float(seg[3 * kTileSeg + s]),
-                                         __uint_as_float(seg[4 * kTileSeg + s])};
-                    hash_level3_tiled<T>(g, ltab[q], htile, q, xp, x);
-                } else if constexpr (TILE == 1) {
-                    ray = seg[kTileSeg + s];
-                    const float fr[3] = {__uint_as_float(seg[2 * kTileSeg + s]),
-                                         __uint_as_float(seg[3 * kTileSeg + s]),
-                                         __uint_as_float(seg[4 * kTileSeg + s])};
-                    const uint32_t cell = seg[5 * kTileSeg + s];
-                    tile_gather3(tile, (int)(cell & 15u), (int)((cell >> 4) & 15u), (int)(cell >> 8), fr, q, x);
-                } else {
-                    sample_inputs<T, false>(g, b, rec[nt], q, x);
-                    ray = b.rec_ray[rec[nt]];
-                }
-                typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
-                ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)ray * 16 + 4 * q));
+            uint32_t ray;
+            if constexpr (TILE == 2) {
+                ray = seg[kTileSeg + sv];
+                const float xp[3] = {__uint_as_float(seg[2 * kTileSeg + sv]), __uint_as_float(seg[3 * kTileSeg + sv]),
+                                     __uint_as_float(seg[4 * kTileSeg + sv])};
+                hash_level3_tiled<T>(g, ltab[q], htile, q, xp, x);
+            } else if constexpr (TILE == 1) {
+                ray = seg[kTileSeg + sv];
+                const float fr[3] = {__uint_as_float(seg[2 * kTileSeg + sv]), __uint_as_float(seg[3 * kTileSeg + sv]),
+                                     __uint_as_float(seg[4 * kTileSeg + sv])};
+                const uint32_t cell = seg[5 * kTileSeg + sv];
+                tile_gather3(tile, (int)(cell & 15u), (int)((cell >> 4) & 15u), (int)(cell >> 8), fr, q, x);
             } else {
-#pragma unroll
-                for (int c = 0; c < 10; ++c) x[c] = 0.f;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) ev[e] = (__bf16)0.0f;
+                sample_inputs<T, false>(g, b, rec[nt], q, x);
+                ray = b.rec_ray[rec[nt]];
             }
+            typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+            const bf8_t ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)ray * 16 + 4 * q));
             // chunk 0: features 3q..3q+2 then encoding slots 0..4; chunk 1: slots 5, 6
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
