@@ -420,14 +420,12 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
         const int64_t bt = first + st * stride + wave;
         const int64_t s = bt * 16 + j;
         const bool valid = bt < hi && s < total;
-        const uint32_t rec = valid ? (uint32_t)s : 0u;   // ray order
+        // ray order; a lane past the end works on sample 0 (in-bounds inputs,
+        // no branches around the loads) with a zero logit gradient, so it
+        // adds nothing to the weight gradients and stores nothing
+        const uint32_t rec = valid ? (uint32_t)s : 0u;
         float x[10];
-        if (valid) {
-            sample_inputs<float, true>(g, b, rec, q, x);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 10; ++c) x[c] = 0.f;
-        }
+        sample_inputs<float, true>(g, b, rec, q, x);
         // forward: layer 0 (40 -> 128), the same products in the same order
         // as the forward kernel's full-input path
         f4_t h1[8];
@@ -506,8 +504,8 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
         float dl[3];
         {
             const float pp[3] = {p0, p1, p2};
-            const float w = valid ? b.rec_w[rec] : 0.f;
-            const uint32_t ray = valid ? b.rec_ray[rec] : 0u;
+            const float w = b.rec_w[rec];
+            const uint32_t ray = b.rec_ray[rec];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const float c = sigmoidf(pp[ch] + lds[AdjLds::kB2 + ch]);
