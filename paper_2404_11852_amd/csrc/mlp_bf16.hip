@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_ray_encode_bf16(RenderBufs b)
     bf8v_t v;
 #pragma unroll
     for (int e = 0; e < 7; ++e) v[e] = (__bf16)x[e];
-    v[7] = (__bf16)0.0f;
+    v[7] = (__bf16)1.0f;   // the constant input of layer 0's bias
     typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
     *(u4_t *)(b.enc + ray * 16 + 4 * q) = __builtin_bit_cast(u4_t, v);
 }
@@ -38,7 +38,7 @@ void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s)
 // Voxel order with LDS-staged bricks (the memory-centric rendering of Sec.
 // IV-A): workgroups claim segments of up to kTileSeg samples of one brick of
 // 8^3 voxels, stage the brick's 9^3 vertices x 12 feature channels in LDS
-// (36 KB as float32) together with the segment's per-sample records (record
+// (44 KB as float32) together with the segment's per-sample records (record
 // index, ray, voxel fractions and cell within the brick, 24 B per sample),
 // and then run the MLP batches from LDS.  Each feature vertex is read from
 // the grid once per segment instead of by every sample near it, and the
@@ -452,7 +452,11 @@ __device__ __forceinline__ void hash_level3_tiled(const GridK &g, const LevelTil
 // activations).  K = 32 per instruction: lane (q, j) supplies 8 consecutive
 // reduction slots.  Layer 0 uses two K-chunks (64 slots >= 39 inputs, same
 // per-lane input assignment as the FP32 kernel: the ten values of lane group
-// q fill chunk 0 and the first two slots of chunk 1).  Layers 1 and 2 take
+// q fill chunk 0 and the first two slots of chunk 1).  Its bias rides in
+// the third slot of chunk 1 of lane groups 0-2: the per-ray encoding row
+// carries a constant 1 there, and the weights hold the three BF16 parts of
+// the float32 bias, whose sum is the bias exactly, so the layer reads no
+// bias from LDS.  Layers 1 and 2 take
 // their B operand from two consecutive 16-row result tiles of the previous
 // layer: chunk c of lane group q covers rows 32c + 4q + (0..3) and
 // 32c + 16 + 4q + (0..3), and the weight fragments are laid out to match.
@@ -465,7 +469,7 @@ constexpr int kBfW0 = 0;                           // [t 8][c 2][lane 64]
 constexpr int kBfW1 = kBfW0 + 8 * 2 * 64;          // [t 8][c 4][lane 64]
 constexpr int kBfW2 = kBfW1 + 8 * 4 * 64;          // [c 4][lane 64]
 constexpr int kBfFrags = kBfW2 + 4 * 64;
-constexpr int kBfB0 = 0, kBfB1 = 128, kBfB2 = 256, kBfFloats = 260;
+constexpr int kBfB1 = 0, kBfB2 = 128, kBfFloats = 132;
 constexpr int kLdsBf16 = kBfFrags * 16 + kBfFloats * 4;
 static_assert(kLdsBf16 + (kFTileFloats + kSegWords) * 4 <= 160 * 1024 - 1024, "brick tile kernel LDS");
 
@@ -482,6 +486,19 @@ __host__ __device__ __forceinline__ int bf_l0_input(int c, int q, int e)
     return slot < 10 ? l0_input(slot, q) : -1;
 }
 
+// slot of chunk 1 (lane groups 0-2) that carries layer 0's bias: input 1.0
+// (encoding slot 7), weight the group's part of the bias
+constexpr int kBfBiasSlot = 2;
+
+// part p of float32 b split into three BF16 values b0 + b1 + b2 = b (each
+// remainder is exact in float32, and the last has at most 8 significant bits)
+__device__ __forceinline__ float bf16_part(float b, int p)
+{
+    const float hi = (float)(__bf16)b, r1 = b - hi;
+    const float mid = (float)(__bf16)r1, r2 = r1 - mid;
+    return p == 0 ? hi : p == 1 ? mid : r2;
+}
+
 __device__ void stage_weights_bf16(const cic_mlp &m, bf8_t *frag, float *fl)
 {
     const int nt = blockDim.x;
@@ -492,7 +509,9 @@ __device__ void stage_weights_bf16(const cic_mlp &m, bf8_t *frag, float *fl)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int src = bf_l0_input(c, q, e);
-            v[e] = (__bf16)(src >= 0 ? m.w0[row * 39 + src] : 0.f);
+            float w = src >= 0 ? m.w0[row * 39 + src] : 0.f;
+            if (c == 1 && e == kBfBiasSlot) w = q < 3 ? bf16_part(m.b0[row], q) : 0.f;   // exact in BF16
+            v[e] = (__bf16)w;
         }
         frag[kBfW0 + i] = v;
     }
@@ -512,10 +531,7 @@ __device__ void stage_weights_bf16(const cic_mlp &m, bf8_t *frag, float *fl)
         for (int e = 0; e < 8; ++e) v[e] = (__bf16)(row < 3 ? m.w2[row * 128 + hid_k(c, q, e)] : 0.f);
         frag[kBfW2 + i] = v;
     }
-    for (int i = threadIdx.x; i < 128; i += nt) {
-        fl[kBfB0 + i] = m.b0[i];
-        fl[kBfB1 + i] = m.b1[i];
-    }
+    for (int i = threadIdx.x; i < 128; i += nt) fl[kBfB1 + i] = m.b1[i];
     if (threadIdx.x < 4) fl[kBfB2 + threadIdx.x] = threadIdx.x < 3 ? m.b2[threadIdx.x] : 0.f;
 }
 
@@ -613,27 +629,28 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
             }
             typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
             const bf8_t ev = __builtin_bit_cast(bf8_t, *(const u4_t *)(b.enc + (int64_t)ray * 16 + 4 * q));
-            // chunk 0: features 3q..3q+2 then encoding slots 0..4; chunk 1: slots 5, 6
+            // chunk 0: features 3q..3q+2 then encoding slots 0..4; chunk 1:
+            // encoding slots 5, 6 and the bias slot's constant 1 (slot 7)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 xin[nt][0][e] = e < 3 ? (__bf16)x[e] : ev[e - 3];
-                xin[nt][1][e] = e < 2 ? ev[5 + e] : (__bf16)0.0f;
+                xin[nt][1][e] = e < 3 ? ev[5 + e] : (__bf16)0.0f;
             }
 
         }
         // layer 0
         __builtin_amdgcn_s_setprio(1);
-        // (each tile's first MFMA takes the bias as its accumulator input)
+        // (the bias comes in through input chunk 1)
         f4_t h1[8][kBfNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const f4_t bias = *(const f4_t *)(fl + kBfB0 + 16 * t + 4 * q);
+            const f4_t zero = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < kBfNT; ++nt)
-                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], c == 0 ? bias : h1[t][nt], 0, 0,
+                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], c == 0 ? zero : h1[t][nt], 0, 0,
                                                                         0);
             }
             __builtin_amdgcn_sched_barrier(0);
