@@ -50,6 +50,9 @@ __global__ __launch_bounds__(128) void k_ray_embed(cic_mlp m, RenderBufs b, floa
     __shared__ float pe[kEmbedRays][28];
     const int o = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kEmbedRays;
+    // a pass over a device-counted set of rays (the holes of a warped frame)
+    // skips the blocks past its count, whose rays have no live samples
+    if (b.n_active && (uint64_t)base >= *b.n_active) return;
     for (int e = threadIdx.x; e < kEmbedRays * 27; e += 128) {
         const int r = e / 27, i = e % 27;
         const int64_t ray = base + r;

@@ -18,6 +18,18 @@ namespace cic {
 
 constexpr int kRayWaves = 4;   // rays (wavefronts) per 256-thread block
 
+// softplus(x) = log(1 + e^x) (x + e^-x above 15), with log1p(e) taken as
+// log(u) e / (u - 1), u = 1 + e: Goldberg's form, accurate to a few ulp when
+// the logarithm is (the hardware log2 and reciprocal here), where the
+// library's log1pf spends about a hundred instructions per call
+__device__ __forceinline__ float softplus_fast(float x)
+{
+    const bool big = x > 15.0f;
+    const float e = expf(big ? -x : x), u = 1.0f + e;
+    const float l = u == 1.0f ? e : __logf(u) * (e * __builtin_amdgcn_rcpf(u - 1.0f));
+    return big ? x + e : l;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
 {
@@ -66,7 +78,7 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
             occ = g.occ ? (g.occ[cell_index(g, i0)] != 0) : true;
             if (occ) {
                 float raw = trilerp1(dens, g, i0, fr, 1, 0);
-                s = softplusf(raw + g.shift) * delta;
+                s = softplus_fast(raw + g.shift) * delta;
             }
         }
         const float incl = wave_incl_scan(s);
