@@ -30,6 +30,17 @@ __device__ __forceinline__ float softplus_fast(float x)
     return big ? x + e : l;
 }
 
+// Opacity 1 - e^-s of optical depth s >= 0: directly where e^-s <= 1/2, and
+// in Kahan's form (1 - u) s / -log(u), u = e^-s, near s = 0, where the
+// subtraction would cancel (a few ulp either way, from the hardware exp2 and
+// log2)
+__device__ __forceinline__ float opacity_fast(float s)
+{
+    const float u = __expf(-s);
+    const float k = u == 1.0f ? s : (1.0f - u) * s * __builtin_amdgcn_rcpf(-__logf(u));
+    return u > 0.5f ? k : 1.0f - u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
 {
@@ -84,12 +95,12 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
         const float incl = wave_incl_scan(s);
         float excl = __shfl_up(incl, 1, kWave);
         if (lane == 0) excl = 0.f;
-        const float Tk = expf(-(carry + excl));
+        const float Tk = __expf(-(carry + excl));
         const bool term = valid && thr > 0.f && Tk < thr;
         const uint64_t tmask = __ballot(term);
         const int first = tmask ? (__ffsll((unsigned long long)tmask) - 1) : kWave;
         const bool live = valid && occ && lane < first;
-        const float w = live ? Tk * (-expm1f(-s)) : 0.f;
+        const float w = live ? Tk * opacity_fast(s) : 0.f;
         const uint64_t lmask = __ballot(live);
         if (live) {
             const uint32_t pos = count + (uint32_t)__popcll(lmask & lanes_below_mask());
@@ -105,7 +116,7 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
         }
         carry += __shfl(incl, kWave - 1, kWave);
     }
-    if (t_stop < 0.f) t_stop = expf(-carry);
+    if (t_stop < 0.f) t_stop = __expf(-carry);
     if (lane == 0) {
         b.count[ray] = count;
         b.info[ray] = RayInfo{tn, delta, t_stop, depth};
