@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
             const uint32_t ray = b.rec_ray[rec];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const float c = sigmoidf(pp[ch] + lds[AdjLds::kB2 + ch]);
+                const float c = sigmoid_hw(pp[ch] + lds[AdjLds::kB2 + ch]);
                 const float dc = valid ? w * bb.d_rgb[3 * (int64_t)ray + ch] : 0.f;
                 dl[ch] = dc * c * (1.f - c);
                 if (valid && q == ch) b.rec_c[3 * (int64_t)rec + ch] = c;

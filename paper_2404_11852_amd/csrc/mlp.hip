@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
             p2 += __shfl_xor(p2, 32, kWave);
             if (valid[nt] && q < 3) {
                 const float logit = pick3(q, p0, p1, p2) + lds[kOffB2 + q];
-                b.rec_c[3 * (int64_t)rec[nt] + q] = sigmoidf(logit);
+                b.rec_c[3 * (int64_t)rec[nt] + q] = sigmoid_hw(logit);
             }
         }
     }

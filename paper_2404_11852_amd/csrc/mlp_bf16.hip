@@ -558,14 +558,6 @@ __device__ __forceinline__ bf8_t relu_bf8(bf8_t v)
     return __builtin_bit_cast(bf8_t, s);
 }
 
-// Output sigmoid of the BF16 path from the hardware base-2 exponential and
-// reciprocal (about 1e-7 relative error, far inside the path's BF16 input
-// rounding): 1 / (1 + 2^(-x log2 e)).
-__device__ __forceinline__ float sigmoid_hw(float x)
-{
-    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * x));
-}
-
 // TILE: 0 = gathers from the grid (ray order, or voxel order through the
 // sample permutation); 1 = voxel order with the brick's features staged in
 // LDS (dense grids); 2 = voxel order with the segment's multi-level encoding
