@@ -42,33 +42,41 @@ int mlp_lds_bytes(int compute)
 
 // Per-ray direction term of layer 0: z0[ray][o] = b0[o] + sum_i W0[o][12+i] pe_i
 // over the 27 direction inputs (d, sin, cos), once per ray with live samples
-// (float32; used by the FP32 MLP in ray order).
-constexpr int kEmbedRays = 16;
+// (float32; used by the FP32 MLP in either order).  A block stages the
+// inputs of kEmbedRays rays in LDS (one sincosf per argument gives both its
+// sine and cosine input), and each of its 128 threads then forms output o for
+// every ray with its 27 weights held in registers.
+#ifndef CIC_EMBED_RAYS
+#define CIC_EMBED_RAYS 64
+#endif
+constexpr int kEmbedRays = CIC_EMBED_RAYS;
 
 __global__ __launch_bounds__(128) void k_ray_embed(cic_mlp m, RenderBufs b, float *z0)
 {
     __shared__ float pe[kEmbedRays][28];
+    __shared__ uint32_t live[kEmbedRays];
     const int o = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kEmbedRays;
     // a pass over a device-counted set of rays (the holes of a warped frame)
     // skips the blocks past its count, whose rays have no live samples
     if (b.n_active && (uint64_t)base >= *b.n_active) return;
-    for (int e = threadIdx.x; e < kEmbedRays * 27; e += 128) {
-        const int r = e / 27, i = e % 27;
-        const int64_t ray = base + r;
-        float v = 0.f;
-        if (ray < b.n && b.count[ray] != 0) {
-            const float *d = b.rays_d + 3 * ray;
-            if (i < 3) {
-                v = d[i];
-            } else {
-                const int k = (i - 3) % 12, c = k >> 2, oc = k & 3;
-                float sn, cs;
-                sincosf(ldexpf(d[c], oc), &sn, &cs);
-                v = i < 15 ? sn : cs;
-            }
+    for (int r = threadIdx.x; r < kEmbedRays; r += 128) live[r] = base + r < b.n ? b.count[base + r] : 0u;
+    __syncthreads();
+    // entries 0..2: the direction; argument k = 4c + octave (k < 12): sine at
+    // 3 + k, cosine at 15 + k
+    for (int e = threadIdx.x; e < kEmbedRays * 15; e += 128) {
+        const int r = e / 15, i = e % 15;
+        if (!live[r]) continue;
+        const float *d = b.rays_d + 3 * (base + r);
+        if (i < 3) {
+            pe[r][i] = d[i];
+        } else {
+            const int k = i - 3, c = k >> 2, oc = k & 3;
+            float sn, cs;
+            sincosf(ldexpf(d[c], oc), &sn, &cs);
+            pe[r][3 + k] = sn;
+            pe[r][15 + k] = cs;
         }
-        pe[r][i] = v;
     }
     __syncthreads();
     float w[27];
@@ -76,12 +84,11 @@ __global__ __launch_bounds__(128) void k_ray_embed(cic_mlp m, RenderBufs b, floa
     for (int i = 0; i < 27; ++i) w[i] = m.w0[o * 39 + 12 + i];
     const float bias = m.b0[o];
     for (int r = 0; r < kEmbedRays; ++r) {
-        const int64_t ray = base + r;
-        if (ray >= b.n || b.count[ray] == 0) continue;
+        if (!live[r]) continue;
         float acc = bias;
 #pragma unroll
         for (int i = 0; i < 27; ++i) acc = fmaf(w[i], pe[r][i], acc);
-        z0[ray * 128 + o] = acc;
+        z0[(base + r) * 128 + o] = acc;
     }
 }
 
