@@ -117,6 +117,26 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
     const f4_t *w2l = (const f4_t *)(lds + kOffW2);
 
     const BatchRange br = xcd_batches(nbatch, kMlpWaves, wave);
+    // Sample s of the wave's batch bt (a lane past the last sample works on
+    // sample 0: in-bounds inputs, no branches around the loads; its colour is
+    // not stored), and its record.
+    auto record_of = [&](int64_t bt, int nt) -> uint32_t {
+        const int64_t s = bt * kBatch + nt * 16 + j;
+        const int64_t sv = s < total ? s : 0;
+        return voxel ? b.perm[sv] : (uint32_t)sv;
+    };
+    // The next batch's record, ray and sample index are loaded during this
+    // batch's layer 1 and its ray's origin, direction and interval during
+    // layer 2, so a batch starts with only its grid gathers outstanding.
+    SampleRay cur[kNT];
+    uint32_t crec[kNT];
+    if (br.first < br.end) {
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            crec[nt] = record_of(br.first, nt);
+            load_sample_ray(b, b.rec_ray[crec[nt]], b.rec_k[crec[nt]], cur[nt]);
+        }
+    }
     for (int64_t bt = br.first; bt < br.end; bt += br.stride) {
         // Wave priority (within this kernel's wavefronts on a SIMD): low
         // while gathering the batch's inputs, raised at each layer so that
@@ -131,14 +151,13 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
         bool valid[kNT];
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
-            const int64_t s = bt * kBatch + nt * 16 + j;
-            valid[nt] = s < total;
-            // a lane past the last sample works on sample 0 (in-bounds
-            // inputs, no branches around the loads); its colour is not stored
-            const int64_t sv = valid[nt] ? s : 0;
-            rec[nt] = voxel ? b.perm[sv] : (uint32_t)sv;
-            sample_inputs<T, !PET>(g, b, rec[nt], q, x[nt]);
+            valid[nt] = bt * kBatch + nt * 16 + j < total;
+            rec[nt] = crec[nt];
+            sample_inputs_from<T, !PET>(g, cur[nt], q, x[nt]);
         }
+        const bool more = bt + br.stride < br.end;
+        uint32_t nrec[kNT], nray[kNT];
+        int nk[kNT];
 
         // layer 0: 40 -> 128 (PET: 12 -> 128 on top of the per-ray term)
         __builtin_amdgcn_s_setprio(1);
@@ -147,7 +166,7 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) {
                 // (every record's ray has live samples, so its row is written)
-                const float *zr = b.z0 + (int64_t)b.rec_ray[rec[nt]] * 128 + 4 * q;
+                const float *zr = b.z0 + (int64_t)cur[nt].ray * 128 + 4 * q;
 #pragma unroll
                 for (int t = 0; t < 8; ++t) h1[t][nt] = *(const f4_t *)(zr + 16 * t);
             }
@@ -191,6 +210,13 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 
         // layer 1: 128 -> 128
         __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            nrec[nt] = record_of(more ? bt + br.stride : 0, nt);
+            nray[nt] = b.rec_ray[nrec[nt]];
+            nk[nt] = b.rec_k[nrec[nt]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         f4_t h2[8][kNT];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -236,6 +262,12 @@ __global__ __launch_bounds__(kMlpWaves * 64, 1) void k_mlp_fwd_f32(GridK g, cic_
 
         // layer 2: 128 -> 3 on the vector ALUs, then sigmoid
         __builtin_amdgcn_s_setprio(3);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            crec[nt] = nrec[nt];
+            load_sample_ray(b, nray[nt], nk[nt], cur[nt]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
             float p0 = 0.f, p1 = 0.f, p2 = 0.f;
