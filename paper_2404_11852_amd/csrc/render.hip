@@ -41,6 +41,31 @@ __device__ __forceinline__ float opacity_fast(float s)
     return u > 0.5f ? k : 1.0f - u;
 }
 
+// Wavefront inclusive prefix sum on DPP lane moves (no LDS round trips):
+// within each row of 16 lanes, shifts by 1, 2, 4 and 8 (a lane without a
+// source adds 0); then rows 1 and 3 add the last lane of rows 0 and 2, and
+// rows 2 and 3 add lane 31.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, BOUND_ZERO));
+}
+__device__ __forceinline__ float wave_incl_scan_dpp(float v)
+{
+    v = dpp_add<0x111, 0xf, true>(v);    // row_shr:1
+    v = dpp_add<0x112, 0xf, true>(v);    // row_shr:2
+    v = dpp_add<0x114, 0xf, true>(v);    // row_shr:4
+    v = dpp_add<0x118, 0xf, true>(v);    // row_shr:8
+    v = dpp_add<0x142, 0xa, false>(v);   // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xc, false>(v);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+// the value of the lane below (0 in lane 0): wave_shr:1
+__device__ __forceinline__ float wave_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
 {
@@ -92,9 +117,8 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
                 s = softplus_fast(raw + g.shift) * delta;
             }
         }
-        const float incl = wave_incl_scan(s);
-        float excl = __shfl_up(incl, 1, kWave);
-        if (lane == 0) excl = 0.f;
+        const float incl = wave_incl_scan_dpp(s);
+        const float excl = wave_shr1(incl);
         const float Tk = __expf(-(carry + excl));
         const bool term = valid && thr > 0.f && Tk < thr;
         const uint64_t tmask = __ballot(term);
@@ -109,12 +133,12 @@ __global__ __launch_bounds__(256) void k_march(GridK g, OptsK op, RenderBufs b)
             if (b.slot_t) b.slot_t[ray * (int64_t)N + pos] = Tk;
         }
         count += (uint32_t)__popcll(lmask);
-        depth += wave_sum(w * tk);
+        depth += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_incl_scan_dpp(w * tk)), kWave - 1));
         if (first < kWave) {
-            t_stop = __shfl(Tk, first, kWave);
+            t_stop = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Tk), first));
             break;
         }
-        carry += __shfl(incl, kWave - 1, kWave);
+        carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
     }
     if (t_stop < 0.f) t_stop = __expf(-carry);
     if (lane == 0) {
