@@ -433,10 +433,15 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s)
 constexpr int kReduceLanes = 16;
 constexpr int kReduceRays = kRayWaves * (kWave / kReduceLanes);   // rays per 256-thread block
 
+// Sum over the 16 lanes of a DPP row, every lane getting it: rotations of
+// the row by 8, 4, 2 and 1 lanes (DPP lane moves, no LDS round trips).
 __device__ __forceinline__ float group16_sum(float v)
 {
-#pragma unroll
-    for (int off = kReduceLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kReduceLanes);
+    static_assert(kReduceLanes == 16, "one ray per DPP row");
+    v = dpp_add<0x128, 0xf, false>(v);   // row_ror:8
+    v = dpp_add<0x124, 0xf, false>(v);   // row_ror:4
+    v = dpp_add<0x122, 0xf, false>(v);   // row_ror:2
+    v = dpp_add<0x121, 0xf, false>(v);   // row_ror:1
     return v;
 }
 
