@@ -630,56 +630,67 @@ __global__ __launch_bounds__(kBfWaves * 64) void k_mlp_fwd_bf16(GridK g, cic_mlp
             }
 
         }
-        // layer 0
+        // layer 0.  A finished pair of row blocks (32 hidden units) becomes
+        // one BF16 input chunk of layer 1 while the next pair's MFMAs issue:
+        // one row block per scheduling region, the pair before it converted in
+        // the region of the next even block.
         __builtin_amdgcn_s_setprio(1);
         // (the bias comes in through input chunk 1)
-        f4_t h1[8][kBfNT];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const f4_t zero = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
-#pragma unroll
-                for (int nt = 0; nt < kBfNT; ++nt)
-                    h1[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nt][c], c == 0 ? zero : h1[t][nt], 0, 0,
-                                                                        0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
         bf8_t hb[4][kBfNT];
+        f4_t h1[2][2][kBfNT];   // [pair parity][block of the pair][tile]
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int t = 0; t <= 8; ++t) {
+            const f4_t zero = f4_t{0.f, 0.f, 0.f, 0.f};
+            if (t < 8) {
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt) hb[c][nt] = relu_bf8(pack_bf8(h1[2 * c][nt], h1[2 * c + 1][nt]));
-        // layer 1
-        __builtin_amdgcn_s_setprio(2);
-        f4_t h2[8][kBfNT];
+                for (int c = 0; c < 2; ++c) {
+                    const bf8_t a = frag[kBfW0 + (t * 2 + c) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const f4_t bias = *(const f4_t *)(fl + kBfB1 + 16 * t + 4 * q);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const bf8_t a = frag[kBfW1 + (t * 4 + c) * 64 + lane];
+                    for (int nt = 0; nt < kBfNT; ++nt)
+                        h1[(t >> 1) & 1][t & 1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a, xin[nt][c], c == 0 ? zero : h1[(t >> 1) & 1][t & 1][nt], 0, 0, 0);
+                }
+            }
+            if ((t & 1) == 0 && t > 0) {
+                const int pr = (t >> 1) - 1;
 #pragma unroll
                 for (int nt = 0; nt < kBfNT; ++nt)
-                    h2[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[c][nt], c == 0 ? bias : h2[t][nt], 0, 0,
-                                                                        0);
+                    hb[pr][nt] = relu_bf8(pack_bf8(h1[pr & 1][0][nt], h1[pr & 1][1][nt]));
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        // layer 2 (one zero-padded tile)
-        __builtin_amdgcn_s_setprio(3);
+        // layer 1, and the output layer (one zero-padded tile) fed pair by
+        // pair: the output MFMA of a finished pair of row blocks issues in the
+        // region of the next even block (the same sums in the same order as
+        // after the whole layer)
+        __builtin_amdgcn_s_setprio(2);
+        f4_t h2[2][2][kBfNT];
         f4_t o3[kBfNT];
         const f4_t bias2 = *(const f4_t *)(fl + kBfB2);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bf8_t a = frag[kBfW2 + c * 64 + lane];
+        for (int t = 0; t <= 8; ++t) {
+            if (t < 8) {
+                const f4_t bias = *(const f4_t *)(fl + kBfB1 + 16 * t + 4 * q);
 #pragma unroll
-            for (int nt = 0; nt < kBfNT; ++nt)
-                o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, relu_bf8(pack_bf8(h2[2 * c][nt], h2[2 * c + 1][nt])),
-                                                                 c == 0 ? bias2 : o3[nt], 0, 0, 0);
+                for (int c = 0; c < 4; ++c) {
+                    const bf8_t a = frag[kBfW1 + (t * 4 + c) * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < kBfNT; ++nt)
+                        h2[(t >> 1) & 1][t & 1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a, hb[c][nt], c == 0 ? bias : h2[(t >> 1) & 1][t & 1][nt], 0, 0, 0);
+                }
+            }
+            if ((t & 1) == 0 && t > 0) {
+                const int pr = (t >> 1) - 1;
+                const bf8_t a = frag[kBfW2 + pr * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kBfNT; ++nt)
+                    o3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a, relu_bf8(pack_bf8(h2[pr & 1][0][nt], h2[pr & 1][1][nt])), pr == 0 ? bias2 : o3[nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
+        __builtin_amdgcn_s_setprio(3);
         // lanes of group 0 hold rows 0..3 (colour channels 0..2) of their sample
 #pragma unroll
         for (int nt = 0; nt < kBfNT; ++nt) {
