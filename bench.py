@@ -88,9 +88,9 @@ COUNTED = {
     "fp32": (3.440e9 + 0.722e9, 0.812, 0.85, ("mlp.hip", "mlp_common.h", "common.h", "kernels.h"),
              "2820d6f02f6b6054"),
     "bf16_ray": (14.682e9 + 5.362e9, 0.849, 0.37, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
-                 "20e6dce30963536c"),
+                 "bfbafbe8ec159c37"),
     "bf16_voxel": (23.610e9 + 6.943e9, 0.245, 0.50, ("mlp_bf16.hip", "mlp_common.h", "common.h", "kernels.h"),
-                   "20e6dce30963536c"),
+                   "bfbafbe8ec159c37"),
     "adjoint": (0.620e9 + 0.156e9, 0.338, 0.61, ("backward.hip", "mlp_common.h", "common.h", "kernels.h"),
                 "ec30f6a486d28f54"),
     # compositing adjoint + brick-segment gradient tiles + tile gather (one step)

@@ -48,9 +48,11 @@ void launch_ray_encode_bf16(const RenderBufs &b, hipStream_t s)
 // Launch shape (measured on the 8-view workload, MLP stage): a BF16 MFMA does
 // a 16-sample tile's layer in 1/16 of the FP32 time, so each batch carries
 // little MFMA work against its dependent gather loads and its weight reads
-// from LDS; 16 wavefronts per CU (128 VGPRs each) with two tiles per batch
-// hide the loads best and read each weight fragment for 32 samples
-// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms).
+// from LDS; 16 wavefronts per CU (a 128-VGPR budget each) with two tiles per
+// batch hide the loads best and read each weight fragment for 32 samples
+// (43.3 ms; 4 waves x 3 workgroups x 2 tiles 56.6 ms, 16 x 1 x 1 tile 44.4 ms;
+// later, with the layers converted pair by pair: 3 tiles x 12 waves 23.95 and
+// 4 tiles x 8 waves 25.2 against 23.54 ms).
 #ifndef CIC_BF_NT
 #define CIC_BF_NT 2
 #endif
