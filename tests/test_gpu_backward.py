@@ -170,7 +170,7 @@ def test_autograd_function_uses_the_leaves_it_is_given():
             t -= 50.0 * t.grad
             t.grad = None
     rgb1, dep1, acc1 = cic.RenderRays.apply(*leaves, to_, td, p.gpu, go)
-    assert float((rgb1 - rgb0).abs().max()) > 1e-4      # the step changed the image
+    assert float((rgb1 - rgb0).detach().abs().max()) > 1e-4      # the step changed the image
     fresh = cic.Model(leaves[0].detach().cpu().numpy(), leaves[1].detach().cpu().numpy(),
                       {k: leaves[2 + i].detach().cpu().numpy() for i, k in enumerate(NAMES[2:])},
                       device="cuda", density_shift=synth.DENSITY_SHIFT)
