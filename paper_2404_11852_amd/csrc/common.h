@@ -273,11 +273,6 @@ __device__ __forceinline__ void hash_level3(const GridK &g, int l, const float x
     lerp3_corners(v, fr, out);
 }
 
-__device__ __forceinline__ float softplusf(float x)
-{
-    return x > 15.0f ? x + expf(-x) : log1pf(expf(x));
-}
-
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 // --------------------------------------------------------------------------
