@@ -3,9 +3,10 @@
 The march kernel takes softplus(x) = log(1 + e^x) in Goldberg's form
 log(u) e / (u - 1), u = 1 + e, and the opacity 1 - e^-s in Kahan's form
 (1 - u) s / -log(u), u = e^-s, near s = 0 (the density activation and the
-per-sample alpha of the compositing, Sec. II-B).  Its logarithm is the hardware log2 times ln 2
-rounded to float, and its e^x the hardware exp2 of x log2(e) with the
-product's rounding error applied as a first-order correction.  These tests
+per-sample alpha of the compositing, Sec. II-B).  Its logarithm is the
+hardware log2 times ln 2 rounded to float, and its e^x the hardware exp2 of
+x log2(e) with the product's rounding error applied as a first-order
+correction.  These tests
 emulate those float32 steps in numpy, with exp2, log2 and the reciprocal
 correctly rounded, and check the relative error bounds quoted for the kernel
 against float64 references.  They exercise the arithmetic of the forms, not
