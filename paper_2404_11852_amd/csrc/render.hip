@@ -200,24 +200,69 @@ __device__ __forceinline__ int run_length(uint64_t heads, int active)
 // One wavefront per ray copies its live samples to their compacted position
 // (ray-order), and in voxel mode tags each with its brick and adds each run
 // of equal bricks to counts[brick] (global counters or an LDS histogram).
+//
+// Ray order: the ray's count and offset are loaded together, and the slots
+// of two 64-sample chunks before any record of them is stored (as far as the
+// compiler knows the stores could alias the slots, so it would not move the
+// second chunk's loads above the first chunk's stores by itself): two round
+// trips to memory per ray instead of three or four (8-view pass: 2.27 to
+// 1.84 ms).  The same form measured slower in voxel mode (4.77 to 6.25 ms with
+// the LDS histogram), which keeps one chunk per step.
+template <bool WITH_T>
+__device__ __forceinline__ void compact_ray_rays(const RenderBufs &b, int64_t ray)
+{
+    const int lane = lane_id();
+    const uint32_t cnt = b.count[ray];
+    const uint32_t off = b.offsets[ray];
+    if (cnt == 0) return;
+    const int64_t slots = ray * (int64_t)b.n_samples;
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 2 * kWave) {
+        // a lane past the count reads slot 0 (the count is positive); a
+        // second chunk past the count stores nothing
+        const uint32_t ja = j0 + lane, jb = ja + kWave;
+        const int64_t sa = slots + (ja < cnt ? ja : 0u), sb = slots + (jb < cnt ? jb : 0u);
+        const uint16_t ka = b.slot_k[sa], kb = b.slot_k[sb];
+        const float wa = b.slot_w[sa], wb = b.slot_w[sb];
+        float ta = 0.f, tb = 0.f;
+        if constexpr (WITH_T) {
+            ta = b.slot_t[sa];
+            tb = b.slot_t[sb];
+        }
+        if (ja < cnt) {
+            b.rec_ray[off + ja] = (uint32_t)ray;
+            b.rec_k[off + ja] = ka;
+            b.rec_w[off + ja] = wa;
+            if constexpr (WITH_T) b.rec_t[off + ja] = ta;
+        }
+        if (jb < cnt) {
+            b.rec_ray[off + jb] = (uint32_t)ray;
+            b.rec_k[off + jb] = kb;
+            b.rec_w[off + jb] = wb;
+            if constexpr (WITH_T) b.rec_t[off + jb] = tb;
+        }
+    }
+}
+
 __device__ __forceinline__ void compact_ray(const GridK &g, const RenderBufs &b, int64_t ray, bool voxel,
                                             uint32_t *counts)
 {
+    if (!voxel) {
+        if (b.rec_t) compact_ray_rays<true>(b, ray);
+        else compact_ray_rays<false>(b, ray);
+        return;
+    }
     const int lane = lane_id();
     const uint32_t cnt = b.count[ray];
     if (cnt == 0) return;
     const uint32_t off = b.offsets[ray];
     const int N = b.n_samples;
     float o[3], d[3];
-    RayInfo inf;
-    if (voxel) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            o[a] = b.rays_o[3 * ray + a];
-            d[a] = b.rays_d[3 * ray + a];
-        }
-        inf = b.info[ray];
+    for (int a = 0; a < 3; ++a) {
+        o[a] = b.rays_o[3 * ray + a];
+        d[a] = b.rays_d[3 * ray + a];
     }
+    const RayInfo inf = b.info[ray];
     for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
         const uint32_t j = j0 + lane;
         const bool act = j < cnt;
@@ -228,19 +273,15 @@ __device__ __forceinline__ void compact_ray(const GridK &g, const RenderBufs &b,
             b.rec_k[off + j] = k;
             b.rec_w[off + j] = b.slot_w[ray * (int64_t)N + j];
             if (b.rec_t) b.rec_t[off + j] = b.slot_t[ray * (int64_t)N + j];
-            if (voxel) {
-                int i0[3];
-                float fr[3], tk;
-                sample_voxel(o, d, inf.tn, inf.delta, k, g, i0, fr, tk);
-                key = brick_of(g, i0);
-                b.rec_key[off + j] = key;
-            }
+            int i0[3];
+            float fr[3], tk;
+            sample_voxel(o, d, inf.tn, inf.delta, k, g, i0, fr, tk);
+            key = brick_of(g, i0);
+            b.rec_key[off + j] = key;
         }
-        if (voxel) {
-            const int active = (int)min(cnt - j0, (uint32_t)kWave);
-            const uint64_t heads = run_heads(key, act);
-            if ((heads >> lane) & 1ull) atomicAdd(&counts[key], (uint32_t)run_length(heads, active));
-        }
+        const int active = (int)min(cnt - j0, (uint32_t)kWave);
+        const uint64_t heads = run_heads(key, act);
+        if ((heads >> lane) & 1ull) atomicAdd(&counts[key], (uint32_t)run_length(heads, active));
     }
 }
 
