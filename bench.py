@@ -76,7 +76,7 @@ def camera(W, H, pose):
 
 # Counted traffic (bytes beyond L2: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000,
 # calibrated on a 1 GiB copy), L2 hit rate and MFMA busy fraction, from the rocprofv3 counter
-# passes summarised in profiles/counters_cfg2_800x800.md, per launch of:
+# passes summarised in profiles/counters_800x800_frame.md, per launch of:
 #   fp32       the headline MLP kernel (ray order, 800x800 frame)
 #   bf16_ray   the BF16 MLP over the 8-view pass (3 chunks), ray order
 #   bf16_voxel the same in voxel order with LDS brick tiles
@@ -590,7 +590,7 @@ def fwd_bwd_bench(steps):
     import synth
     import paper_2404_11852_amd as cic
     from paper_2404_11852_amd import _lib
-    ex = synth.get_config("cfg5").extra
+    ex = synth.get_config("train8192_views8").extra
     W = H = 800
     f, cx, cy = synth.intrinsics(W, H)
     poses = synth.sphere_poses(8, seed=3)

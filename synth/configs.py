@@ -1,13 +1,16 @@
 """The five workload configurations (sizes and seeds; no arithmetic).
 
-cfg1  64x64 frame, 32^3 grid, 64 samples/ray, no skipping, no termination.
-cfg2  800x800 frame, 160^3 grid, 256 samples/ray, occupancy skip, termination
-      at transmittance 1e-4.
-cfg3  cfg2 scene on a 32-frame orbit (1 deg/frame); references every 16th
-      frame; targets warped from the nearest reference, holes re-rendered.
-cfg4  8 views of the cfg2 scene on the radius-4 sphere in one launch; FP16 grid
-      storage and BF16 MLP.
-cfg5  one fwd+bwd step on 8192 rays drawn from 8 views of a hidden scene.
+frame64_grid32        64x64 frame, 32^3 grid, 64 samples/ray, no skipping,
+                      no termination.
+frame800_grid160      800x800 frame, 160^3 grid, 256 samples/ray, occupancy
+                      skip, termination at transmittance 1e-4.
+orbit32_frame800      the 800x800 scene on a 32-frame orbit (1 deg/frame);
+                      references every 16th frame; targets warped from the
+                      nearest reference, holes re-rendered.
+views8_frame800_fp16  8 views of the 800x800 scene on the radius-4 sphere in
+                      one launch; FP16 grid storage and BF16 MLP.
+train8192_views8      one fwd+bwd step on 8192 rays drawn from 8 views of a
+                      hidden scene.
 """
 from dataclasses import dataclass, field
 
@@ -34,12 +37,12 @@ class Config:
 
 
 CONFIGS = {
-    "cfg1": Config("cfg1", 64, 64, 32, 64, False, 0.0),
-    "cfg2": Config("cfg2", 800, 800, 160, 256, True, 1e-4),
-    "cfg3": Config("cfg3", 800, 800, 160, 256, True, 1e-4, n_frames=32, ref_every=16),
-    "cfg4": Config("cfg4", 800, 800, 160, 256, True, 1e-4, n_views=8, pose_seed=2,
+    "frame64_grid32": Config("frame64_grid32", 64, 64, 32, 64, False, 0.0),
+    "frame800_grid160": Config("frame800_grid160", 800, 800, 160, 256, True, 1e-4),
+    "orbit32_frame800": Config("orbit32_frame800", 800, 800, 160, 256, True, 1e-4, n_frames=32, ref_every=16),
+    "views8_frame800_fp16": Config("views8_frame800_fp16", 800, 800, 160, 256, True, 1e-4, n_views=8, pose_seed=2,
                    storage="f16", compute="bf16"),
-    "cfg5": Config("cfg5", 800, 800, 160, 256, False, 1e-4, n_views=8, pose_seed=3,
+    "train8192_views8": Config("train8192_views8", 800, 800, 160, 256, False, 1e-4, n_views=8, pose_seed=3,
                    n_rays=8192,
                    extra={"gt_scene_seed": 10, "gt_mlp_seed": 20, "model_grid_seed": 11,
                           "model_mlp_seed": 21, "ray_seed": 12}),

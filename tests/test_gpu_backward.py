@@ -112,7 +112,7 @@ def test_backward_full_size_training_step():
     grids N(0, 0.01) (seed 11), MLP seed 21, 8192 rays from 8 views,
     256 samples, termination at 1e-4."""
     print_case("backward full size 160^3, 8192 rays, N=256")
-    cfg = synth.get_config("cfg5")
+    cfg = synth.get_config("train8192_views8")
     ex = cfg.extra
     o, d = _training_rays()
     gd, gf = synth.make_scene(160, seed=ex["gt_scene_seed"])

@@ -60,10 +60,10 @@ def test_render_rays_random(n_samples):
     print("max err rgb %.2e depth %.2e acc %.2e" % (e1, e2, e3))
 
 
-def test_render_frame_cfg1():
+def test_render_frame_64x64():
     """64x64 frame, 32^3 grid, 64 samples, no skipping/termination."""
     import paper_2404_11852_amd as cic
-    print_case("render_frame cfg1")
+    print_case("render_frame 64x64")
     p = Pair(32, seed=0, mlp_seed=1)
     gc, oc = cams(64, 64, synth.orbit_pose(0))
     n_eval = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -105,12 +105,12 @@ def test_render_frame_skip_and_termination(order):
         assert torch.equal(rgb, r2)
 
 
-def test_render_frame_cfg2_sampled():
+def test_render_frame_800x800_sampled():
     """Full 800x800, 160^3, 256 samples with skipping and termination, in the
     launch configuration the benchmark times; 3000 seeded pixels checked
     against the oracle one by one."""
     import paper_2404_11852_amd as cic
-    print_case("render_frame cfg2 800x800 sampled")
+    print_case("render_frame 800x800 sampled")
     p = Pair(160, seed=0, mlp_seed=1, occupancy=True)
     gc, oc = cams(800, 800, synth.orbit_pose(0))
     go = cic.make_opts(256, et_threshold=1e-4, use_occupancy=True, order=0)
@@ -118,7 +118,7 @@ def test_render_frame_cfg2_sampled():
     pix = synth.pixel_subset(800, 800, 3000, seed=7)
     orgb, odz, oacc, diag = oracle.render_pixels(p.orc, oracle.opts(256, 1e-4, True), oc, pix)
     e, nflag = compare(to_np(rgb)[pix], orgb, margin=diag["margin"])
-    print("cfg2 sampled max err %.2e, %d flagged" % (e, nflag))
+    print("800x800 sampled max err %.2e, %d flagged" % (e, nflag))
     # void pixels agree away from the opacity cut
     am = diag["acc_margin"]
     assert np.array_equal(np.isinf(to_np(dz)[pix])[am > 1e-3], np.isinf(odz)[am > 1e-3])
